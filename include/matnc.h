@@ -1,0 +1,228 @@
+/*
+ * matnc.h -- C ABI of libmatnc: sliced multi-amplitude tensor-network
+ * contraction on one MI355X (gfx950).
+ *
+ * The problem (Supplementary Information Sec. II, main text "Multiple-
+ * amplitude simulation"): a circuit becomes a tensor network whose n output
+ * indices (one per qubit) are uncontracted.  Fixing every output index to a
+ * bit of b gives a closed network whose value is the amplitude <b|psi>;
+ * leaving some output indices open gives a block of correlated amplitudes.
+ * k bitstrings give k networks that differ only in their bright tensors
+ * (tensors holding an output index).  A contraction order (TNCO, a binary
+ * tree) is given; every intermediate tensor computed before the subtree
+ * meets an output index is shared by all bitstrings that agree on the
+ * outputs below it (the reuse tree, Eq. (1)).  A sliced index set turns the
+ * network into the sum of 2^|S| smaller networks (Supplementary Sec. IV.B).
+ * Linear XEB is F = (2^n / K) sum |a|^2 - 1 over the K amplitudes (the mean
+ * of x = 2^n p under Eq. (2) is 1 + F).
+ *
+ * Conventions shared by all calls:
+ *  - every index has dimension 2; index ids are non-negative ints;
+ *  - a tensor's data is complex128, interleaved (re, im), row-major over the
+ *    tensor's index list with the FIRST index most significant;
+ *  - bitstring words are uint64 with bit q = value of qubit q;
+ *  - open-leg results: the amplitude block of group i has 2^n_open entries,
+ *    entry j has the t-th open qubit (ascending qubit id) equal to bit t of j;
+ *  - device amplitude buffers are complex128 interleaved, [k][2^n_open][2].
+ *
+ * Ownership: every host array passed in is copied before the call returns.
+ * The library never allocates device memory: all device storage is the
+ * caller's workspace (matnc_plan_bind) or the caller's output buffers.  The
+ * plan owns host metadata and, while bound, the captured HIP graph.
+ *
+ * Errors: every call returns MATNC_OK (0) or one of the MATNC_E_* codes and
+ * never throws or aborts across the ABI.  matnc_last_error() returns a
+ * thread-local message for the last failing call of the calling thread.  On
+ * error, output arguments are left unchanged.
+ *
+ * Threading: one plan per stream; a plan must not be used from two threads
+ * at once.  Different plans are independent.
+ */
+#ifndef MATNC_H
+#define MATNC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MATNC_OK = 0,
+  MATNC_E_INVALID = 1, /* malformed input (ids, tree, bitstrings, sizes)       */
+  MATNC_E_RANK = 2,    /* an intermediate exceeds max_rank after slicing      */
+  MATNC_E_NOMEM = 3,   /* workspace smaller than matnc_plan_info's figure     */
+  MATNC_E_HIP = 4,     /* a HIP runtime call failed; its text is in the message */
+  MATNC_E_STATE = 5    /* call out of order (e.g. execute before bind)        */
+};
+
+enum {
+  MATNC_C64 = 0,  /* complex64: FP32 storage, FP32 MFMA / FMA               */
+  MATNC_CHALF = 1 /* complex-half: FP16 storage with a power-of-two exponent
+                     per tensor instance, FP16 MFMA with FP32 accumulation   */
+};
+
+typedef struct matnc_network_s *matnc_network;
+typedef struct matnc_plan_s *matnc_plan;
+typedef struct matnc_queue_s *matnc_queue;
+
+/* Version string of the library ("matnc <semver> gfx950"). */
+const char *matnc_version(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *matnc_last_error(void);
+
+/*
+ * matnc_network_create -- the tensor network of a circuit (Supplementary
+ * Sec. II: |0>, one- and two-qubit gates as rank-1/2/4 tensors, possibly
+ * fused).
+ *   n_tensors              number of tensors, >= 1
+ *   ranks[n_tensors]       rank of each tensor, 0..20
+ *   index_ids[sum ranks]   index ids of tensor 0, then tensor 1, ...
+ *   data_c128              2 * sum(2^rank) doubles, tensors concatenated
+ *   n_qubits               1..64
+ *   output_index_of_qubit[n_qubits]  the output index id of each qubit
+ * Every output index must occur on exactly one tensor, every other index on
+ * exactly two (no hyper-indices).  Errors: MATNC_E_INVALID.
+ */
+int matnc_network_create(int n_tensors, const int *ranks, const int *index_ids,
+                         const double *data_c128, int n_qubits,
+                         const int *output_index_of_qubit, matnc_network *out);
+int matnc_network_destroy(matnc_network net);
+
+/*
+ * matnc_plan_create -- static multi-amplitude plan (main text: the reuse
+ * tree makes contraction pattern, cost and memory known before running).
+ *   pairs[2*(n_tensors-1)]  contraction tree in SSA form: step j contracts
+ *                           ids pairs[2j], pairs[2j+1] into id n_tensors+j;
+ *                           every id is consumed exactly once, the last
+ *                           step is the root
+ *   sliced_ids[n_sliced]    bond indices to slice (Supplementary Sec. IV.B);
+ *                           slice id sigma assigns bit j of sigma to
+ *                           sliced_ids[j]; 2^n_sliced slices (n_sliced <= 40)
+ *   open_qubits[n_open]     qubits whose output index stays open (distinct)
+ *   k, bitstrings[k]        batch; bits of open qubits are ignored, bits at
+ *                           positions >= n_qubits must be zero; duplicates
+ *                           are allowed (each gets its own result row)
+ *   precision               MATNC_C64 or MATNC_CHALF
+ *   max_rank                cap on every tensor's rank after slicing, <= 32
+ *   slice_batch             slices contracted per launch sequence (>= 1);
+ *                           the workspace grows with it
+ * The library derives the reuse structure (distinct projections of the
+ * batch onto the outputs below each tree node, gather maps between a node
+ * and its children), the storage order of every intermediate, the kernel
+ * choice per node and the static memory plan.
+ * Errors: MATNC_E_INVALID, MATNC_E_RANK.
+ */
+int matnc_plan_create(matnc_network net, const int *pairs, int n_sliced,
+                      const int *sliced_ids, int n_open, const int *open_qubits,
+                      int64_t k, const uint64_t *bitstrings, int precision,
+                      int max_rank, int slice_batch, matnc_plan *out);
+
+typedef struct {
+  double cmac_single;       /* S: complex MACs of one amplitude, one slice   */
+  double cmac_multi;        /* S_k: complex MACs of the batch, one slice     */
+  double cmac_invariant;    /* part of S_k in nodes that see no sliced index */
+  double cmac_total;        /* all slices: invariant once + dependent x 2^|S| */
+  double bytes_per_slice;   /* algorithmic HBM bytes of one slice (dependent) */
+  double bytes_invariant;   /* algorithmic HBM bytes of the invariant nodes  */
+  int64_t n_slices;         /* 2^n_sliced                                    */
+  int64_t n_amplitudes;     /* k * 2^n_open                                  */
+  int64_t n_unique;         /* distinct closed bitstrings                    */
+  int max_rank;             /* largest tensor rank after slicing             */
+  int n_nodes;              /* contraction steps                             */
+  int n_mfma_nodes;         /* steps routed to the MFMA GEMM kernel          */
+  int n_launches_per_batch; /* kernel launches per slice batch               */
+  size_t workspace_bytes;   /* device workspace needed by matnc_plan_bind    */
+  size_t cache_bytes;       /* part of it holding slice-invariant tensors    */
+} matnc_plan_info_t;
+
+int matnc_plan_info(matnc_plan plan, matnc_plan_info_t *info);
+
+/*
+ * matnc_plan_set_tensor -- replace the data of tensor t (same index list);
+ * complex128 as in matnc_network_create.  Invalidates the slice-invariant
+ * cache; takes effect at the next execute.  Errors: MATNC_E_INVALID.
+ */
+int matnc_plan_set_tensor(matnc_plan plan, int t, const double *data_c128);
+
+/*
+ * matnc_plan_bind -- attach the caller's device workspace (at least
+ * workspace_bytes, 256-byte aligned) and HIP stream (hipStream_t, may be
+ * NULL for the null stream), upload leaf variants, gather maps and offset
+ * tables, and capture the per-batch launch sequence as a HIP graph.
+ * The workspace must stay allocated until the plan is destroyed or re-bound.
+ * Errors: MATNC_E_NOMEM, MATNC_E_HIP, MATNC_E_INVALID (misaligned).
+ */
+int matnc_plan_bind(matnc_plan plan, void *dev_workspace, size_t bytes, void *hip_stream);
+
+/*
+ * matnc_execute -- contract slices [slice_begin, slice_end) and ADD their
+ * contributions into amps_dev (complex128, [k][2^n_open]) in FP64, one
+ * slice after another in increasing slice id (so any split of a slice range
+ * into calls gives bit-identical results).  Slice-invariant intermediates
+ * are computed on the first call after bind/set_tensor and kept (stem
+ * cache).  Asynchronous on the bound stream.
+ * Errors: MATNC_E_STATE (not bound), MATNC_E_INVALID (range), MATNC_E_HIP.
+ */
+int matnc_execute(matnc_plan plan, int64_t slice_begin, int64_t slice_end, double *amps_dev);
+
+/*
+ * matnc_xeb -- linear XEB of the amplitudes in amps_dev over all
+ * k * 2^n_open entries: F = (2^n_qubits / K) sum |a|^2 - 1, a deterministic
+ * FP64 reduction written to xeb_dev[0].  Asynchronous on the bound stream.
+ */
+int matnc_xeb(matnc_plan plan, const double *amps_dev, double *xeb_dev);
+
+int matnc_plan_destroy(matnc_plan plan);
+
+/*
+ * Uneven batches: several bound plans (each with its own workspace and
+ * circuit) executed over all of their slices as one queue, with one FP64
+ * amplitude buffer and one XEB slot per plan.
+ *   matnc_queue_execute(q, amps_dev[n], xeb_dev[n]) contracts every slice
+ *   of every plan (adding into amps_dev[i]) and writes XEB of plan i to
+ *   xeb_dev[i].  All plans must be bound to the same stream.
+ */
+int matnc_queue_create(int n_plans, const matnc_plan *plans, matnc_queue *out);
+int matnc_queue_execute(matnc_queue q, double *const *amps_dev, double *xeb_dev);
+int matnc_queue_destroy(matnc_queue q);
+
+/*
+ * matnc_contract -- one pairwise contraction with bit-permuted layouts
+ * (the kernel behind every tree node; exposed for testing and tuning).
+ * All indices have dimension 2.  For tensor X in {A, B, C}, pos_X[i] is the
+ * storage bit position of the i-th index of that class:
+ *   C[m, n] = sum_k A[m, k] * B[k, n]
+ *   m bits: posA_m[nm], posC_m[nm];  n bits: posB_n[nn], posC_n[nn];
+ *   k bits: posA_k[nk], posB_k[nk].
+ * rank(A) = nm + nk, rank(B) = nn + nk, rank(C) = nm + nn (each <= 32) and
+ * each tensor's positions form a permutation of 0..rank-1.
+ * A, B, C are device pointers to complex64 (float2) data; batch instances
+ * are contiguous: C[i] = A[i] x B[i] for i < batch (stride 2^rank).
+ * kernel: -1 = library choice, 0 = streaming (VALU), 1 = MFMA GEMM with
+ * the first tile configuration that fits, 100 + c = MFMA tile configuration
+ * c (0 <= c < matnc_mfma_config_count()).
+ * dev_scratch: caller's device buffer of at least
+ * matnc_contract_scratch_bytes() bytes, 256-byte aligned, holding the
+ * offset tables of the call (the library allocates nothing).  The call
+ * uploads them and waits for that copy; the contraction itself is
+ * asynchronous on hip_stream.  Errors: MATNC_E_INVALID, MATNC_E_NOMEM
+ * (scratch too small), MATNC_E_HIP.
+ */
+size_t matnc_contract_scratch_bytes(void);
+int matnc_mfma_config_count(void);
+int matnc_contract(const void *A, const void *B, void *C, int64_t batch,
+                   int nm, int nn, int nk,
+                   const int *posA_m, const int *posA_k,
+                   const int *posB_k, const int *posB_n,
+                   const int *posC_m, const int *posC_n,
+                   int kernel, void *dev_scratch, size_t scratch_bytes,
+                   void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MATNC_H */

@@ -1,0 +1,31 @@
+// Host-side launchers of the device kernels (all asynchronous on `st`).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "desc.h"
+
+namespace matnc {
+
+// complex64
+hipError_t launch_stream(const NodeDesc& d, uint64_t ws, const int64_t* sig, hipStream_t st);
+int mfma_config_count();
+bool mfma_config_fits(int cfg, int mbits, int nbits, int kbits);
+hipError_t launch_mfma(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st);
+hipError_t launch_slice_sum(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t k, int open_bits,
+                            double* amps, hipStream_t st);
+
+// complex-half
+bool chalf_available();
+hipError_t launch_stream_h(const NodeDesc& d, uint64_t ws, const int64_t* sig, hipStream_t st);
+int mfma_h_config_count();
+bool mfma_h_config_fits(int cfg, int mbits, int nbits, int kbits);
+hipError_t launch_mfma_h(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st);
+hipError_t launch_slice_sum_h(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t k,
+                              int open_bits, double* amps, hipStream_t st);
+
+// shared
+hipError_t launch_xeb(const double* amps, int64_t count, int n_qubits, double* out, hipStream_t st);
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t st);
+
+}  // namespace matnc

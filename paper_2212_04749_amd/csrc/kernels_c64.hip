@@ -1,0 +1,455 @@
+// complex64 kernels of the contraction path (gfx950).
+//
+//  * k_stream_*: one pairwise step C[m, n] = sum_k A[m, k] B[k, n] whose small
+//    operand B has at most 2^8 elements: HBM-bound, one lane per m, lanes
+//    walking the lowest storage bits of A and C, B read with block-uniform
+//    addresses (scalar loads) when a block stays inside one instance.
+//  * k_mfma_*: the same step when N and K are large: a complex GEMM on
+//    v_mfma_f32_32x32x2f32 through the real embedding
+//    [Ar Ai] x [[Br, Bi], [-Bi, Br]] = [Cr Ci] (8 real flops per complex
+//    MAC, so MFMA flops equal complex flops), LDS-staged, double-buffered
+//    tiles, with the bit permutation of each operand folded into its tile
+//    loads through the offset tables of desc.h.  M runs along the MFMA
+//    column (lane-contiguous) so output stores are coalesced along m.
+//  * k_slice_sum: FP64 accumulation of the root instances into the caller's
+//    amplitudes, slices added one by one in slice-id order.
+//  * k_xeb: deterministic FP64 sum of |a|^2 and the linear XEB estimate.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "desc.h"
+#include "kernels.h"
+
+namespace matnc {
+
+__device__ __forceinline__ uint32_t tlook(const uint32_t* __restrict__ T, uint32_t x) {
+  return T[x & 255u] + T[256 + ((x >> 8) & 255u)] + T[512 + ((x >> 16) & 255u)] + T[768 + (x >> 24)];
+}
+
+// offset of coordinate hi * 256 + lo (lo < 256)
+__device__ __forceinline__ uint32_t tlook_split(const uint32_t* __restrict__ T, uint32_t hi, uint32_t lo) {
+  return T[lo] + T[256 + (hi & 255u)] + T[512 + ((hi >> 8) & 255u)] + T[768 + (hi >> 16)];
+}
+
+__device__ __forceinline__ int64_t operand_instance(const OpDesc& o, const int32_t* gmap, int64_t j,
+                                                    int64_t s, int64_t sigma) {
+  int64_t v = (int64_t)gmap[j] * o.nsv;
+  for (int t = 0; t < o.nsb; ++t) v += ((sigma >> o.sbit[t]) & 1) << t;
+  if (o.dep) v += s * (int64_t)o.w_child;
+  return v;
+}
+
+__device__ __forceinline__ void cmac(float2& c, float2 a, float2 b) {
+  c.x = fmaf(a.x, b.x, c.x);
+  c.x = fmaf(-a.y, b.y, c.x);
+  c.y = fmaf(a.x, b.y, c.y);
+  c.y = fmaf(a.y, b.x, c.y);
+}
+
+// ---------------------------------------------------------------------------
+// streaming kernels
+
+// Blocks of 256 lanes cover 256 consecutive m of one instance (mbits >= 8).
+template <int KB, int NB>
+__global__ __launch_bounds__(256) void k_stream_wide(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
+  const uint32_t* __restrict__ tab = reinterpret_cast<const uint32_t*>(ws + d.tab_off);
+  const int32_t* __restrict__ glA = reinterpret_cast<const int32_t*>(ws + d.A.gmap_off);
+  const int32_t* __restrict__ glB = reinterpret_cast<const int32_t*>(ws + d.B.gmap_off);
+  const int64_t bpi = (int64_t)1 << (d.mbits - 8);
+  const int64_t nblk = d.n_inst * bpi;
+  const int64_t sigma0 = sig[0];
+  const uint32_t lo = threadIdx.x;
+  const uint32_t oa_lo = tab[TAB_AM * kTabSize + lo];
+  const uint32_t oc_lo = tab[TAB_CM * kTabSize + lo];
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t inst = blk >> (d.mbits - 8);
+    const uint32_t hi = (uint32_t)(blk & (bpi - 1));
+    const int64_t s = d.dep ? inst / d.w : 0;
+    const int64_t j = d.dep ? inst - s * d.w : inst;
+    const int64_t sigma = sigma0 + s;
+    const int64_t ai = operand_instance(d.A, glA, j, s, sigma);
+    const int64_t bi = operand_instance(d.B, glB, j, s, sigma);
+    const float2* __restrict__ pa = reinterpret_cast<const float2*>(ws + d.A.off + ai * d.A.inst_bytes);
+    const float2* __restrict__ pb = reinterpret_cast<const float2*>(ws + d.B.off + bi * d.B.inst_bytes);
+    float2* __restrict__ pc = reinterpret_cast<float2*>(ws + d.c_off + inst * d.c_inst_bytes);
+    const uint32_t* TA = tab + TAB_AM * kTabSize;
+    const uint32_t* TC = tab + TAB_CM * kTabSize;
+    const uint32_t oa = oa_lo + TA[256 + (hi & 255u)] + TA[512 + ((hi >> 8) & 255u)] + TA[768 + (hi >> 16)];
+    const uint32_t oc = oc_lo + TC[256 + (hi & 255u)] + TC[512 + ((hi >> 8) & 255u)] + TC[768 + (hi >> 16)];
+    float2 a[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) a[k] = pa[oa + tab[TAB_AK * kTabSize + k]];
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+      float2 c = make_float2(0.f, 0.f);
+      const uint32_t bn = tab[TAB_BN * kTabSize + n];
+#pragma unroll
+      for (int k = 0; k < KB; ++k) cmac(c, a[k], pb[bn + tab[TAB_BK * kTabSize + k]]);
+      pc[oc + tab[TAB_CN * kTabSize + n]] = c;
+    }
+  }
+}
+
+// One lane per (instance, m) with m < 2^mbits < 256.
+template <int KB, int NB>
+__global__ __launch_bounds__(256) void k_stream_narrow(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
+  const uint32_t* __restrict__ tab = reinterpret_cast<const uint32_t*>(ws + d.tab_off);
+  const int32_t* __restrict__ glA = reinterpret_cast<const int32_t*>(ws + d.A.gmap_off);
+  const int32_t* __restrict__ glB = reinterpret_cast<const int32_t*>(ws + d.B.gmap_off);
+  const int64_t total = d.n_inst << d.mbits;
+  const uint32_t mmask = (1u << d.mbits) - 1u;
+  const int64_t sigma0 = sig[0];
+  for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < total; g += (int64_t)gridDim.x * 256) {
+    const int64_t inst = g >> d.mbits;
+    const uint32_t m = (uint32_t)g & mmask;
+    const int64_t s = d.dep ? inst / d.w : 0;
+    const int64_t j = d.dep ? inst - s * d.w : inst;
+    const int64_t sigma = sigma0 + s;
+    const int64_t ai = operand_instance(d.A, glA, j, s, sigma);
+    const int64_t bi = operand_instance(d.B, glB, j, s, sigma);
+    const float2* __restrict__ pa = reinterpret_cast<const float2*>(ws + d.A.off + ai * d.A.inst_bytes);
+    const float2* __restrict__ pb = reinterpret_cast<const float2*>(ws + d.B.off + bi * d.B.inst_bytes);
+    float2* __restrict__ pc = reinterpret_cast<float2*>(ws + d.c_off + inst * d.c_inst_bytes);
+    const uint32_t oa = tab[TAB_AM * kTabSize + m];
+    const uint32_t oc = tab[TAB_CM * kTabSize + m];
+    float2 a[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) a[k] = pa[oa + tab[TAB_AK * kTabSize + k]];
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+      float2 c = make_float2(0.f, 0.f);
+      const uint32_t bn = tab[TAB_BN * kTabSize + n];
+#pragma unroll
+      for (int k = 0; k < KB; ++k) cmac(c, a[k], pb[bn + tab[TAB_BK * kTabSize + k]]);
+      pc[oc + tab[TAB_CN * kTabSize + n]] = c;
+    }
+  }
+}
+
+// Any shape: one lane per (instance, m, n), loops over k.  Used when the
+// small operand is too large for the templated kernels.
+__global__ __launch_bounds__(256) void k_stream_generic(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
+  const uint32_t* __restrict__ tab = reinterpret_cast<const uint32_t*>(ws + d.tab_off);
+  const int32_t* __restrict__ glA = reinterpret_cast<const int32_t*>(ws + d.A.gmap_off);
+  const int32_t* __restrict__ glB = reinterpret_cast<const int32_t*>(ws + d.B.gmap_off);
+  const int cb = d.mbits + d.nbits;
+  const int64_t total = d.n_inst << cb;
+  const int64_t sigma0 = sig[0];
+  const uint64_t kcount = (uint64_t)1 << d.kbits;
+  for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < total; g += (int64_t)gridDim.x * 256) {
+    const int64_t inst = g >> cb;
+    const uint64_t mn = (uint64_t)g & (((uint64_t)1 << cb) - 1);
+    const uint32_t m = (uint32_t)(mn & (((uint64_t)1 << d.mbits) - 1));
+    const uint32_t n = (uint32_t)(mn >> d.mbits);
+    const int64_t s = d.dep ? inst / d.w : 0;
+    const int64_t j = d.dep ? inst - s * d.w : inst;
+    const int64_t sigma = sigma0 + s;
+    const int64_t ai = operand_instance(d.A, glA, j, s, sigma);
+    const int64_t bi = operand_instance(d.B, glB, j, s, sigma);
+    const float2* __restrict__ pa = reinterpret_cast<const float2*>(ws + d.A.off + ai * d.A.inst_bytes);
+    const float2* __restrict__ pb = reinterpret_cast<const float2*>(ws + d.B.off + bi * d.B.inst_bytes);
+    float2* __restrict__ pc = reinterpret_cast<float2*>(ws + d.c_off + inst * d.c_inst_bytes);
+    const uint32_t oa = tlook(tab + TAB_AM * kTabSize, m);
+    const uint32_t ob = tlook(tab + TAB_BN * kTabSize, n);
+    float2 c = make_float2(0.f, 0.f);
+    for (uint64_t k = 0; k < kcount; ++k) {
+      const uint32_t kk = (uint32_t)k;
+      cmac(c, pa[oa + tlook(tab + TAB_AK * kTabSize, kk)], pb[ob + tlook(tab + TAB_BK * kTabSize, kk)]);
+    }
+    pc[tlook(tab + TAB_CM * kTabSize, m) + tlook(tab + TAB_CN * kTabSize, n)] = c;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// MFMA complex GEMM
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// Tile: TM = 32*RM*WM values of m, TN = 16*RN*WN complex n, TK complex k.
+template <int RM, int RN, int WM, int WN, int TK>
+__global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int TM = 32 * RM * WM;
+  constexpr int TN = 16 * RN * WN;
+  constexpr int EA = TK * TM / NT;
+  constexpr int EB = TK * TN / NT;
+  static_assert(EA * NT == TK * TM && EB * NT == TK * TN, "tile must split evenly over threads");
+  constexpr int APL = TK * TM + 32;        // plane stride (floats), padded
+  constexpr int BPL = TK * TN + 16;
+  __shared__ float As[2][2 * APL];
+  __shared__ float Bs[2][2 * BPL];
+
+  const uint32_t* __restrict__ tab = reinterpret_cast<const uint32_t*>(ws + d.tab_off);
+  const int32_t* __restrict__ glA = reinterpret_cast<const int32_t*>(ws + d.A.gmap_off);
+  const int32_t* __restrict__ glB = reinterpret_cast<const int32_t*>(ws + d.B.gmap_off);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave % WM;
+  const int wn = wave / WM;
+
+  const int64_t mt_count = (int64_t)1 << (d.mbits - __builtin_ctz(TM));
+  const int64_t nt_count = (int64_t)1 << (d.nbits - __builtin_ctz(TN));
+  const int64_t tiles = mt_count * nt_count;
+  const int ksteps = 1 << (d.kbits - __builtin_ctz(TK));
+  const int64_t sigma0 = sig[0];
+
+  for (int64_t blk = blockIdx.x; blk < d.n_inst * tiles; blk += gridDim.x) {
+    const int64_t inst = blk / tiles;
+    const int64_t t = blk - inst * tiles;
+    const uint32_t m0 = (uint32_t)((t % mt_count) * TM);
+    const uint32_t n0 = (uint32_t)((t / mt_count) * TN);
+    const int64_t s = d.dep ? inst / d.w : 0;
+    const int64_t j = d.dep ? inst - s * d.w : inst;
+    const int64_t sigma = sigma0 + s;
+    const int64_t ai = operand_instance(d.A, glA, j, s, sigma);
+    const int64_t bi = operand_instance(d.B, glB, j, s, sigma);
+    const float2* __restrict__ pa = reinterpret_cast<const float2*>(ws + d.A.off + ai * d.A.inst_bytes);
+    const float2* __restrict__ pb = reinterpret_cast<const float2*>(ws + d.B.off + bi * d.B.inst_bytes);
+    float2* __restrict__ pc = reinterpret_cast<float2*>(ws + d.c_off + inst * d.c_inst_bytes);
+
+    // per-thread load coordinates (fixed across k steps)
+    uint32_t aoff[EA], boff[EB];
+    int akk[EA], bkk[EB], amm[EA], bnn[EB];
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int flat = e * NT + tid;
+      amm[e] = flat % TM;
+      akk[e] = flat / TM;
+      aoff[e] = tlook(tab + TAB_AM * kTabSize, m0 + amm[e]) + tab[TAB_AK * kTabSize + akk[e]];
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int flat = e * NT + tid;
+      bnn[e] = flat % TN;
+      bkk[e] = flat / TN;
+      boff[e] = tlook(tab + TAB_BN * kTabSize, n0 + bnn[e]) + tab[TAB_BK * kTabSize + bkk[e]];
+    }
+    float2 ra[EA], rb[EB];
+    auto gload = [&](int ks) {
+      const uint32_t k0 = (uint32_t)ks * TK;
+      const uint32_t kba = tlook(tab + TAB_AK * kTabSize, k0);
+      const uint32_t kbb = tlook(tab + TAB_BK * kTabSize, k0);
+#pragma unroll
+      for (int e = 0; e < EA; ++e) ra[e] = pa[aoff[e] + kba];
+#pragma unroll
+      for (int e = 0; e < EB; ++e) rb[e] = pb[boff[e] + kbb];
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int e = 0; e < EA; ++e) {
+        As[buf][akk[e] * TM + amm[e]] = ra[e].x;
+        As[buf][APL + akk[e] * TM + amm[e]] = ra[e].y;
+      }
+#pragma unroll
+      for (int e = 0; e < EB; ++e) {
+        Bs[buf][bkk[e] * TN + bnn[e]] = rb[e].x;
+        Bs[buf][BPL + bkk[e] * TN + bnn[e]] = rb[e].y;
+      }
+    };
+
+    floatx16 acc[RM][RN];
+#pragma unroll
+    for (int i = 0; i < RM; ++i)
+#pragma unroll
+      for (int q = 0; q < RN; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][q][r] = 0.f;
+
+    const int half = lane >> 5;     // 0: real part row of the embedding, 1: imaginary
+    const int l32 = lane & 31;
+    const int dsel = l32 & 1;       // 0: real column, 1: imaginary column
+    const int ncol = l32 >> 1;
+    // which B plane feeds this lane, and with which sign
+    const int bplane = (half ^ dsel) ? BPL : 0;  // (0,0)->Br (0,1)->Bi (1,0)->Bi (1,1)->Br
+    const float bsign = (half == 1 && dsel == 0) ? -1.f : 1.f;
+    const int aplane = half ? APL : 0;
+
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int ks = 0; ks < ksteps; ++ks) {
+      const int buf = ks & 1;
+      if (ks + 1 < ksteps) gload(ks + 1);
+#pragma unroll
+      for (int kk = 0; kk < TK; ++kk) {
+        float yv[RM], xv[RN];
+#pragma unroll
+        for (int i = 0; i < RM; ++i) yv[i] = As[buf][aplane + kk * TM + (wm * RM + i) * 32 + l32];
+#pragma unroll
+        for (int q = 0; q < RN; ++q) xv[q] = bsign * Bs[buf][bplane + kk * TN + (wn * RN + q) * 16 + ncol];
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+#pragma unroll
+          for (int q = 0; q < RN; ++q)
+            acc[i][q] = __builtin_amdgcn_mfma_f32_32x32x2f32(xv[q], yv[i], acc[i][q], 0, 0, 0);
+      }
+      if (ks + 1 < ksteps) lstore(buf ^ 1);
+      __syncthreads();
+    }
+
+    // epilogue: lane holds C[m][n] (re, im) in registers (r, r+1), r even
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+      const uint32_t m = m0 + (wm * RM + i) * 32 + l32;
+      const uint32_t om = tlook(tab + TAB_CM * kTabSize, m);
+#pragma unroll
+      for (int q = 0; q < RN; ++q) {
+#pragma unroll
+        for (int r = 0; r < 16; r += 2) {
+          const int row = 8 * (r >> 2) + 4 * half + (r & 3);
+          const uint32_t n = n0 + (wn * RN + q) * 16 + (row >> 1);
+          pc[om + tlook(tab + TAB_CN * kTabSize, n)] = make_float2(acc[i][q][r], acc[i][q][r + 1]);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+
+__global__ __launch_bounds__(256) void k_slice_sum(OpDesc root, uint64_t ws, const int64_t* __restrict__ sig,
+                                                   int nb, int64_t k, int open_bits, double2* __restrict__ amps) {
+  const int32_t* __restrict__ gmap = reinterpret_cast<const int32_t*>(ws + root.gmap_off);
+  const int64_t total = k << open_bits;
+  const int64_t sigma0 = sig[0];
+  const int64_t omask = ((int64_t)1 << open_bits) - 1;
+  for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < total; g += (int64_t)gridDim.x * 256) {
+    const int64_t i = g >> open_bits;
+    const int64_t o = g & omask;
+    double2 acc = amps[g];
+    for (int s = 0; s < nb; ++s) {
+      const int64_t inst = operand_instance(root, gmap, i, s, sigma0 + s);
+      const float2 v = reinterpret_cast<const float2*>(ws + root.off + inst * root.inst_bytes)[o];
+      acc.x += (double)v.x;
+      acc.y += (double)v.y;
+    }
+    amps[g] = acc;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_xeb(const double2* __restrict__ amps, int64_t count, int n_qubits,
+                                              double* __restrict__ out) {
+  __shared__ double red[1024];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += 1024) {
+    const double2 a = amps[i];
+    acc += a.x * a.x + a.y * a.y;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 512; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = ldexp(red[0] / (double)count, n_qubits) - 1.0;
+}
+
+__global__ void k_set_i64(int64_t* p, int64_t v) {
+  if (threadIdx.x == 0) p[0] = v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static unsigned grid_for(int64_t blocks) {
+  const int64_t cap = 256 * 1024;  // grid-stride beyond this
+  return (unsigned)(blocks < 1 ? 1 : (blocks > cap ? cap : blocks));
+}
+
+template <int KB, int NB>
+static hipError_t launch_stream_t(const NodeDesc& d, uint64_t ws, const int64_t* sig, hipStream_t st) {
+  if (d.mbits >= 8) {
+    const int64_t blocks = d.n_inst << (d.mbits - 8);
+    hipLaunchKernelGGL((k_stream_wide<KB, NB>), dim3(grid_for(blocks)), dim3(256), 0, st, d, ws, sig);
+  } else {
+    const int64_t blocks = ((d.n_inst << d.mbits) + 255) / 256;
+    hipLaunchKernelGGL((k_stream_narrow<KB, NB>), dim3(grid_for(blocks)), dim3(256), 0, st, d, ws, sig);
+  }
+  return hipGetLastError();
+}
+
+template <int KB>
+static hipError_t launch_stream_n(const NodeDesc& d, uint64_t ws, const int64_t* sig, hipStream_t st) {
+  switch (d.nbits) {
+    case 0: return launch_stream_t<KB, 1>(d, ws, sig, st);
+    case 1: return launch_stream_t<KB, 2>(d, ws, sig, st);
+    case 2: return launch_stream_t<KB, 4>(d, ws, sig, st);
+    case 3: return launch_stream_t<KB, 8>(d, ws, sig, st);
+    case 4: return launch_stream_t<KB, 16>(d, ws, sig, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_stream(const NodeDesc& d, uint64_t ws, const int64_t* sig, hipStream_t st) {
+  if (d.n_inst == 0) return hipSuccess;
+  if (d.kbits <= 4 && d.nbits <= 4) {
+    switch (d.kbits) {
+      case 0: return launch_stream_n<1>(d, ws, sig, st);
+      case 1: return launch_stream_n<2>(d, ws, sig, st);
+      case 2: return launch_stream_n<4>(d, ws, sig, st);
+      case 3: return launch_stream_n<8>(d, ws, sig, st);
+      case 4: return launch_stream_n<16>(d, ws, sig, st);
+    }
+  }
+  const int64_t blocks = ((d.n_inst << (d.mbits + d.nbits)) + 255) / 256;
+  hipLaunchKernelGGL(k_stream_generic, dim3(grid_for(blocks)), dim3(256), 0, st, d, ws, sig);
+  return hipGetLastError();
+}
+
+struct MfmaCfg {
+  int tm_bits, tn_bits, tk_bits;
+};
+
+static const MfmaCfg kMfmaCfgs[] = {
+    {7, 5, 3},  // 0: RM=2 RN=1 WM=2 WN=2, TK=8  -> TM=128, TN=32
+    {7, 6, 3},  // 1: RM=2 RN=2 WM=2 WN=2, TK=8  -> TM=128, TN=64
+    {6, 5, 3},  // 2: RM=1 RN=1 WM=2 WN=2, TK=8  -> TM=64,  TN=32
+    {8, 5, 3},  // 3: RM=4 RN=1 WM=2 WN=2, TK=8  -> TM=256, TN=32
+};
+
+int mfma_config_count() { return (int)(sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0])); }
+
+bool mfma_config_fits(int cfg, int mbits, int nbits, int kbits) {
+  if (cfg < 0 || cfg >= mfma_config_count()) return false;
+  const MfmaCfg& c = kMfmaCfgs[cfg];
+  return mbits >= c.tm_bits && nbits >= c.tn_bits && kbits >= c.tk_bits;
+}
+
+hipError_t launch_mfma(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
+  if (d.n_inst == 0) return hipSuccess;
+  if (!mfma_config_fits(cfg, d.mbits, d.nbits, d.kbits)) return hipErrorInvalidValue;
+  const MfmaCfg& c = kMfmaCfgs[cfg];
+  const int64_t tiles = ((int64_t)1 << (d.mbits - c.tm_bits)) * ((int64_t)1 << (d.nbits - c.tn_bits));
+  const unsigned grid = grid_for(d.n_inst * tiles);
+  switch (cfg) {
+    case 0: hipLaunchKernelGGL((k_mfma<2, 1, 2, 2, 8>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 1: hipLaunchKernelGGL((k_mfma<2, 2, 2, 2, 8>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 2: hipLaunchKernelGGL((k_mfma<1, 1, 2, 2, 8>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 3: hipLaunchKernelGGL((k_mfma<4, 1, 2, 2, 8>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_slice_sum(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t k, int open_bits,
+                            double* amps, hipStream_t st) {
+  const int64_t total = k << open_bits;
+  if (total == 0 || nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slice_sum, dim3(grid_for((total + 255) / 256)), dim3(256), 0, st, root, ws, sig, nb, k,
+                     open_bits, reinterpret_cast<double2*>(amps));
+  return hipGetLastError();
+}
+
+hipError_t launch_xeb(const double* amps, int64_t count, int n_qubits, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_xeb, dim3(1), dim3(1024), 0, st, reinterpret_cast<const double2*>(amps), count, n_qubits, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, st, p, v);
+  return hipGetLastError();
+}
+
+}  // namespace matnc

@@ -1,0 +1,935 @@
+// libmatnc: plan construction, binding, execution and the C ABI.
+//
+// Method (main text "Multiple-amplitude simulation with static and optimal
+// tensor reuse"; Supplementary Secs. III-IV): the k networks of a bitstring
+// batch share every tensor computed before the first output index is met.
+// For a node v of the contraction tree, all bitstrings with the same
+// projection onto the closed outputs below v share v's tensor, so v is
+// computed once per distinct projection (w(v) instances) -- the optimal
+// reuse whose cost is Eq. (1).  Instances are computed breadth-first per
+// tree level in batched launches, each reading its operands through gather
+// maps.  Slicing (Sec. IV.B) fixes the sliced indices per slice; nodes with
+// no sliced index below them are computed once and kept (stem cache), the
+// others once per slice, and the root instances of every slice are added in
+// FP64 into the caller's amplitudes in slice order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <exception>
+#include <limits>
+#include <map>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/matnc.h"
+#include "desc.h"
+#include "kernels.h"
+#include "plan.h"
+
+using namespace matnc;
+
+struct matnc_network_s {
+  Network net;
+};
+struct matnc_plan_s {
+  Plan p;
+};
+struct matnc_queue_s {
+  std::vector<matnc_plan> plans;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Err : std::runtime_error {
+  int code;
+  Err(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw Err(code, msg); }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(MATNC_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    f();
+    return MATNC_OK;
+  } catch (const Err& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host memory exhausted";
+    return MATNC_E_INVALID;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return MATNC_E_INVALID;
+  } catch (...) {
+    g_err = "unknown error";
+    return MATNC_E_INVALID;
+  }
+}
+
+constexpr uint64_t kAlign = 256;
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// ---------------------------------------------------------------------------
+// plan construction
+
+void build_structure(Plan& P) {
+  const Network& N = P.net;
+  const int nt = N.n_tensors;
+  P.n_nodes = 2 * nt - 1;
+  P.nodes.assign(P.n_nodes, PNode());
+
+  std::unordered_map<int, int> out_qubit;  // output index -> qubit
+  for (int q = 0; q < N.n_qubits; ++q) out_qubit[N.out_index[q]] = q;
+  std::vector<char> is_open(N.n_qubits, 0);
+  for (int q : P.open_qubits) is_open[q] = 1;
+  std::unordered_map<int, int> slice_bit;
+  for (size_t j = 0; j < P.sliced.size(); ++j) slice_bit[P.sliced[j]] = (int)j;
+
+  // free index sets (unordered for now)
+  std::vector<std::vector<int>> freeset(P.n_nodes);
+  for (int t = 0; t < nt; ++t) {
+    PNode& L = P.nodes[t];
+    std::vector<std::pair<int, int>> sl;
+    for (int i : N.idx[t]) {
+      auto oq = out_qubit.find(i);
+      if (oq != out_qubit.end() && !is_open[oq->second]) {
+        L.omask |= 1ull << oq->second;
+        continue;
+      }
+      auto sb = slice_bit.find(i);
+      if (sb != slice_bit.end()) {
+        sl.push_back({sb->second, i});
+        continue;
+      }
+      freeset[t].push_back(i);
+    }
+    std::sort(sl.begin(), sl.end());
+    for (auto& x : sl) {
+      L.sl_bits.push_back(x.first);
+      L.sl_index.push_back(x.second);
+    }
+    if ((int)L.sl_bits.size() > kMaxLeafSliced) fail(MATNC_E_INVALID, "a tensor holds more than 16 sliced indices");
+    L.dep = !L.sl_bits.empty();
+  }
+  // internal nodes; death time of contracted indices
+  std::unordered_map<int, int> death;
+  for (int j = 0; j < nt - 1; ++j) {
+    const int v = nt + j;
+    const int a = P.pairs[j].first, b = P.pairs[j].second;
+    PNode& V = P.nodes[v];
+    V.a = a;
+    V.b = b;
+    P.nodes[a].parent = v;
+    P.nodes[b].parent = v;
+    V.omask = P.nodes[a].omask | P.nodes[b].omask;
+    V.dep = P.nodes[a].dep || P.nodes[b].dep;
+    std::vector<int> fa = freeset[a], fb = freeset[b];
+    std::sort(fa.begin(), fa.end());
+    std::sort(fb.begin(), fb.end());
+    std::vector<int> shared, out;
+    std::set_intersection(fa.begin(), fa.end(), fb.begin(), fb.end(), std::back_inserter(shared));
+    std::set_symmetric_difference(fa.begin(), fa.end(), fb.begin(), fb.end(), std::back_inserter(out));
+    for (int i : shared) death[i] = v;
+    freeset[v] = out;
+  }
+  // storage order: latest death lowest; open outputs (never contracted)
+  // first, in ascending qubit order
+  auto key_of = [&](int i) {
+    auto oq = out_qubit.find(i);
+    if (oq != out_qubit.end()) return std::make_pair(-1LL, (long long)oq->second);
+    auto d = death.find(i);
+    const long long dt = d == death.end() ? (long long)INT_MAX : (long long)d->second;
+    return std::make_pair(-dt, (long long)i);
+  };
+  P.max_rank = 0;
+  for (int v = 0; v < P.n_nodes; ++v) {
+    std::vector<int> f = freeset[v];
+    std::sort(f.begin(), f.end(), [&](int x, int y) { return key_of(x) < key_of(y); });
+    P.nodes[v].idx = f;
+    P.max_rank = std::max<int>(P.max_rank, (int)f.size());
+  }
+  if (P.max_rank > P.max_rank_cap)
+    fail(MATNC_E_RANK, "largest tensor has rank " + std::to_string(P.max_rank) + " > max_rank " +
+                           std::to_string(P.max_rank_cap));
+  if (P.max_rank > 32) fail(MATNC_E_RANK, "ranks above 32 are not supported");
+}
+
+void build_reuse(Plan& P) {
+  const int nt = P.net.n_tensors;
+  // distinct projections per node
+  std::map<uint64_t, std::vector<uint64_t>> cache;
+  for (int v = 0; v < P.n_nodes; ++v) {
+    const uint64_t m = P.nodes[v].omask;
+    auto it = cache.find(m);
+    if (it == cache.end()) {
+      std::vector<uint64_t> ks;
+      ks.reserve(P.words.size());
+      for (uint64_t w : P.words) ks.push_back(w & m);
+      std::sort(ks.begin(), ks.end());
+      ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
+      it = cache.emplace(m, std::move(ks)).first;
+    }
+    P.nodes[v].keys = it->second;
+  }
+  auto find = [](const std::vector<uint64_t>& ks, uint64_t u) -> int32_t {
+    auto it = std::lower_bound(ks.begin(), ks.end(), u);
+    return (int32_t)(it - ks.begin());
+  };
+  for (int v = nt; v < P.n_nodes; ++v) {
+    PNode& V = P.nodes[v];
+    const PNode& A = P.nodes[V.a];
+    const PNode& B = P.nodes[V.b];
+    V.ga.resize(V.keys.size());
+    V.gb.resize(V.keys.size());
+    for (size_t j = 0; j < V.keys.size(); ++j) {
+      V.ga[j] = find(A.keys, V.keys[j] & A.omask);
+      V.gb[j] = find(B.keys, V.keys[j] & B.omask);
+    }
+  }
+  const PNode& R = P.nodes[P.n_nodes - 1];
+  P.rootmap.resize(P.words.size());
+  for (size_t i = 0; i < P.words.size(); ++i) P.rootmap[i] = find(R.keys, P.words[i] & R.omask);
+  P.n_unique = (int64_t)P.nodes[P.n_nodes - 1].keys.size();
+  {
+    std::vector<uint64_t> u = P.words;
+    std::sort(u.begin(), u.end());
+    P.n_unique = (int64_t)(std::unique(u.begin(), u.end()) - u.begin());
+  }
+}
+
+void build_steps(Plan& P) {
+  const int nt = P.net.n_tensors;
+  P.n_mfma = 0;
+  P.cmac_single = P.cmac_multi = P.cmac_inv = P.cmac_total = 0;
+  P.bytes_slice = P.bytes_inv = 0;
+  const double nsl = std::ldexp(1.0, (int)P.sliced.size());
+  const double eb = P.elem_bytes;
+  for (int v = nt; v < P.n_nodes; ++v) {
+    PNode& V = P.nodes[v];
+    const PNode& ca = P.nodes[V.a];
+    const PNode& cb = P.nodes[V.b];
+    V.swap = cb.idx.size() > ca.idx.size();
+    const PNode& A = V.swap ? cb : ca;
+    const PNode& B = V.swap ? ca : cb;
+    if (V.swap) std::swap(V.ga, V.gb);
+    std::vector<int> sa(A.idx), sb(B.idx);
+    std::vector<int> sa_sorted(sa), sb_sorted(sb);
+    std::sort(sa_sorted.begin(), sa_sorted.end());
+    std::sort(sb_sorted.begin(), sb_sorted.end());
+    V.M.clear();
+    V.N.clear();
+    V.K.clear();
+    for (int i : A.idx) {
+      if (std::binary_search(sb_sorted.begin(), sb_sorted.end(), i))
+        V.K.push_back(i);
+      else
+        V.M.push_back(i);
+    }
+    for (int i : B.idx)
+      if (!std::binary_search(sa_sorted.begin(), sa_sorted.end(), i)) V.N.push_back(i);
+    const int mb = (int)V.M.size(), nb = (int)V.N.size(), kb = (int)V.K.size();
+    V.kernel = 0;
+    V.cfg = -1;
+    if (nb + kb > 8) {
+      // MFMA tiles: prefer the widest N tile that fits
+      const int order[] = {1, 0, 3, 2};
+      for (int c : order) {
+        if (mfma_config_fits(c, mb, nb, kb)) {
+          V.kernel = 1;
+          V.cfg = c;
+          break;
+        }
+      }
+    }
+    if (V.kernel == 1) ++P.n_mfma;
+    const double cm = std::ldexp(1.0, mb + nb + kb);
+    const double w = (double)V.keys.size();
+    P.cmac_single += cm;
+    P.cmac_multi += w * cm;
+    const double by = eb * (w * std::ldexp(1.0, (int)V.idx.size()) +
+                            (double)A.keys.size() * std::ldexp(1.0, (int)A.idx.size()) +
+                            (double)B.keys.size() * std::ldexp(1.0, (int)B.idx.size()));
+    if (V.dep) {
+      P.cmac_total += w * cm * nsl;
+      P.bytes_slice += by;
+    } else {
+      P.cmac_inv += w * cm;
+      P.cmac_total += w * cm;
+      P.bytes_inv += by;
+    }
+  }
+}
+
+// offset tables of one class: entry e of level L = sum over bits t of e of
+// 2^pos(index 8L+t)
+void fill_table(uint32_t* T, const std::vector<int>& order, const std::vector<int>& storage) {
+  std::vector<int> pos(order.size());
+  for (size_t t = 0; t < order.size(); ++t) {
+    auto it = std::find(storage.begin(), storage.end(), order[t]);
+    pos[t] = (int)(it - storage.begin());
+  }
+  for (int L = 0; L < kTabLevels; ++L)
+    for (int e = 0; e < kTabEntries; ++e) {
+      uint32_t off = 0;
+      for (int t = 0; t < 8; ++t) {
+        const size_t bit = (size_t)(8 * L + t);
+        if (((e >> t) & 1) && bit < pos.size()) off += 1u << pos[bit];
+      }
+      T[L * kTabEntries + e] = off;
+    }
+}
+
+struct Buf {
+  int node;
+  uint64_t size;
+  int t0, t1;
+};
+
+void build_memory(Plan& P) {
+  const int nt = P.net.n_tensors;
+  const int root = P.n_nodes - 1;
+  // schedule: invariant internal nodes, then dependent ones, each in SSA order
+  P.prologue.clear();
+  P.loop.clear();
+  for (int v = nt; v < P.n_nodes; ++v) (P.nodes[v].dep ? P.loop : P.prologue).push_back(v);
+  int t = 0;
+  for (int v : P.prologue) P.nodes[v].time = t++;
+  for (int v : P.loop) P.nodes[v].time = t++;
+  const int t_end = t + 1;
+
+  // static region
+  uint64_t off = 0;
+  P.sigma_off = off;
+  off += kAlign;
+  for (int v = nt; v < P.n_nodes; ++v) {
+    PNode& V = P.nodes[v];
+    V.tab_off = off;
+    off = align_up(off + (uint64_t)TAB_COUNT * kTabSize * 4);
+    V.ga_off = off;
+    off = align_up(off + V.ga.size() * 4);
+    V.gb_off = off;
+    off = align_up(off + V.gb.size() * 4);
+  }
+  P.rootmap_off = off;
+  off = align_up(off + P.rootmap.size() * 4);
+  // leaf variants: keys x 2^nsb instances
+  for (int l = 0; l < nt; ++l) {
+    PNode& L = P.nodes[l];
+    L.inst_elems = 1ull << L.idx.size();
+    L.off = off;
+    L.buf_bytes = (uint64_t)L.keys.size() * (1ull << L.sl_bits.size()) * L.inst_elems * P.elem_bytes;
+    off = align_up(off + L.buf_bytes);
+  }
+  P.static_bytes = off;
+
+  // intermediates
+  std::vector<Buf> bufs;
+  for (int v = nt; v < P.n_nodes; ++v) {
+    PNode& V = P.nodes[v];
+    V.inst_elems = 1ull << V.idx.size();
+    const uint64_t ninst = (uint64_t)V.keys.size() * (V.dep ? (uint64_t)P.batch : 1ull);
+    V.buf_bytes = align_up(ninst * V.inst_elems * P.elem_bytes);
+    int t1;
+    if (v == root)
+      t1 = t_end;
+    else if (!V.dep && P.nodes[V.parent].dep)
+      t1 = t_end;  // stem cache: kept across all slice batches
+    else
+      t1 = P.nodes[V.parent].time;
+    bufs.push_back({v, V.buf_bytes, V.time, t1});
+  }
+  std::sort(bufs.begin(), bufs.end(), [](const Buf& x, const Buf& y) {
+    return x.size != y.size ? x.size > y.size : x.t0 < y.t0;
+  });
+  std::vector<std::pair<uint64_t, uint64_t>> placed_range;  // per placed buf
+  std::vector<const Buf*> placed;
+  uint64_t arena = 0;
+  P.cache_bytes = 0;
+  for (const Buf& b : bufs) {
+    std::vector<std::pair<uint64_t, uint64_t>> busy;
+    for (size_t i = 0; i < placed.size(); ++i)
+      if (!(placed[i]->t1 < b.t0 || b.t1 < placed[i]->t0)) busy.push_back(placed_range[i]);
+    std::sort(busy.begin(), busy.end());
+    uint64_t cur = 0;
+    for (auto& r : busy) {
+      if (r.first >= cur + b.size) break;
+      cur = std::max(cur, r.second);
+    }
+    placed.push_back(&b);
+    placed_range.push_back({cur, cur + b.size});
+    P.nodes[b.node].off = P.static_bytes + cur;
+    arena = std::max(arena, cur + b.size);
+    if (b.t1 == t_end && b.node != root) P.cache_bytes += b.size;
+  }
+  P.workspace_bytes = align_up(P.static_bytes + arena);
+}
+
+void fill_leaf_data(Plan& P, int l, unsigned char* dst) {
+  const Network& N = P.net;
+  const PNode& L = P.nodes[l];
+  const std::vector<int>& ix = N.idx[l];
+  const int r = (int)ix.size();
+  std::unordered_map<int, int> out_qubit;
+  for (int q = 0; q < N.n_qubits; ++q) out_qubit[N.out_index[q]] = q;
+  // role of each original axis
+  std::vector<int> kind(r), arg(r);  // 0 closed output (qubit), 1 sliced (t), 2 free (pos)
+  for (int a = 0; a < r; ++a) {
+    const int i = ix[a];
+    auto fp = std::find(L.idx.begin(), L.idx.end(), i);
+    if (fp != L.idx.end()) {
+      kind[a] = 2;
+      arg[a] = (int)(fp - L.idx.begin());
+      continue;
+    }
+    auto sp = std::find(L.sl_index.begin(), L.sl_index.end(), i);
+    if (sp != L.sl_index.end()) {
+      kind[a] = 1;
+      arg[a] = (int)(sp - L.sl_index.begin());
+      continue;
+    }
+    kind[a] = 0;
+    arg[a] = out_qubit.at(i);
+  }
+  const uint64_t nsv = 1ull << L.sl_bits.size();
+  const uint64_t ne = L.inst_elems;
+  const std::vector<double>& src = N.data[l];
+  uint64_t inst = 0;
+  for (size_t u = 0; u < L.keys.size(); ++u) {
+    for (uint64_t sv = 0; sv < nsv; ++sv, ++inst) {
+      for (uint64_t e = 0; e < ne; ++e) {
+        uint64_t flat = 0;
+        for (int a = 0; a < r; ++a) {
+          uint64_t bit;
+          if (kind[a] == 0)
+            bit = (L.keys[u] >> arg[a]) & 1;
+          else if (kind[a] == 1)
+            bit = (sv >> arg[a]) & 1;
+          else
+            bit = (e >> arg[a]) & 1;
+          flat |= bit << (r - 1 - a);
+        }
+        const double re = src[2 * flat], im = src[2 * flat + 1];
+        const uint64_t d = inst * ne + e;
+        if (P.elem_bytes == 8) {
+          float* f = reinterpret_cast<float*>(dst) + 2 * d;
+          f[0] = (float)re;
+          f[1] = (float)im;
+        }
+      }
+    }
+  }
+}
+
+OpDesc operand_desc(const Plan& P, int child, uint64_t gmap_off) {
+  const PNode& C = P.nodes[child];
+  OpDesc o;
+  std::memset(&o, 0, sizeof(o));
+  o.off = C.off;
+  o.inst_bytes = C.inst_elems * P.elem_bytes;
+  o.gmap_off = gmap_off;
+  o.w_child = (int32_t)C.keys.size();
+  const bool leaf = child < P.net.n_tensors;
+  o.dep = (!leaf && C.dep) ? 1 : 0;
+  o.nsb = leaf ? (int32_t)C.sl_bits.size() : 0;
+  o.nsv = 1 << o.nsb;
+  for (int t = 0; t < o.nsb; ++t) o.sbit[t] = (int8_t)C.sl_bits[t];
+  return o;
+}
+
+NodeDesc node_desc(const Plan& P, int v, int nb) {
+  const PNode& V = P.nodes[v];
+  NodeDesc d;
+  std::memset(&d, 0, sizeof(d));
+  const int ca = V.swap ? V.b : V.a;
+  const int cb = V.swap ? V.a : V.b;
+  d.A = operand_desc(P, ca, V.ga_off);
+  d.B = operand_desc(P, cb, V.gb_off);
+  d.c_off = V.off;
+  d.c_inst_bytes = V.inst_elems * P.elem_bytes;
+  d.tab_off = V.tab_off;
+  d.w = (int32_t)V.keys.size();
+  d.dep = V.dep ? 1 : 0;
+  d.n_inst = (int64_t)d.w * (V.dep ? nb : 1);
+  d.mbits = (int32_t)V.M.size();
+  d.nbits = (int32_t)V.N.size();
+  d.kbits = (int32_t)V.K.size();
+  return d;
+}
+
+OpDesc root_desc(const Plan& P) {
+  const int root = P.n_nodes - 1;
+  return operand_desc(P, root, P.rootmap_off);
+}
+
+void launch_node(const Plan& P, const PNode& V, const NodeDesc& d, hipStream_t st) {
+  const int64_t* sig = reinterpret_cast<const int64_t*>(P.ws + P.sigma_off);
+  hipError_t e;
+  if (P.precision == MATNC_C64) {
+    e = V.kernel == 1 ? launch_mfma(d, V.cfg, P.ws, sig, st) : launch_stream(d, P.ws, sig, st);
+  } else {
+    e = V.kernel == 1 ? launch_mfma_h(d, V.cfg, P.ws, sig, st) : launch_stream_h(d, P.ws, sig, st);
+  }
+  hip_check(e, "kernel launch");
+}
+
+void launch_batch(const Plan& P, int nb, hipStream_t st) {
+  for (int v : P.loop) launch_node(P, P.nodes[v], node_desc(P, v, nb), st);
+}
+
+void release_graph(Plan& P) {
+  if (P.graph_exec) (void)hipGraphExecDestroy(P.graph_exec);
+  if (P.graph) (void)hipGraphDestroy(P.graph);
+  P.graph_exec = nullptr;
+  P.graph = nullptr;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+const char* matnc_version(void) { return "matnc 0.1.0 gfx950"; }
+
+const char* matnc_last_error(void) { return g_err.c_str(); }
+
+int matnc_network_create(int n_tensors, const int* ranks, const int* index_ids, const double* data_c128,
+                         int n_qubits, const int* output_index_of_qubit, matnc_network* out) {
+  return guarded([&] {
+    if (!out || !ranks || !index_ids || !data_c128 || !output_index_of_qubit)
+      fail(MATNC_E_INVALID, "null argument");
+    if (n_tensors < 1) fail(MATNC_E_INVALID, "n_tensors must be >= 1");
+    if (n_qubits < 1 || n_qubits > 64) fail(MATNC_E_INVALID, "n_qubits must be in 1..64");
+    auto h = new matnc_network_s();
+    std::unique_ptr<matnc_network_s> guard(h);
+    Network& N = h->net;
+    N.n_tensors = n_tensors;
+    N.n_qubits = n_qubits;
+    N.idx.resize(n_tensors);
+    N.data.resize(n_tensors);
+    size_t ip = 0, dp = 0;
+    std::unordered_map<int, int> count;
+    for (int t = 0; t < n_tensors; ++t) {
+      const int r = ranks[t];
+      if (r < 0 || r > 20) fail(MATNC_E_INVALID, "tensor rank must be in 0..20");
+      N.idx[t].assign(index_ids + ip, index_ids + ip + r);
+      ip += r;
+      std::vector<int> s = N.idx[t];
+      std::sort(s.begin(), s.end());
+      if (std::adjacent_find(s.begin(), s.end()) != s.end())
+        fail(MATNC_E_INVALID, "tensor " + std::to_string(t) + " repeats an index");
+      for (int i : s) {
+        if (i < 0) fail(MATNC_E_INVALID, "index ids must be >= 0");
+        ++count[i];
+      }
+      const size_t ne = (size_t)1 << r;
+      N.data[t].assign(data_c128 + 2 * dp, data_c128 + 2 * (dp + ne));
+      dp += ne;
+    }
+    N.out_index.assign(output_index_of_qubit, output_index_of_qubit + n_qubits);
+    std::unordered_map<int, int> seen_out;
+    for (int q = 0; q < n_qubits; ++q) {
+      const int i = N.out_index[q];
+      if (seen_out.count(i)) fail(MATNC_E_INVALID, "two qubits share an output index");
+      seen_out[i] = q;
+      if (count[i] != 1) fail(MATNC_E_INVALID, "output index of qubit " + std::to_string(q) + " must occur once");
+    }
+    for (auto& kv : count)
+      if (!seen_out.count(kv.first) && kv.second != 2)
+        fail(MATNC_E_INVALID, "index " + std::to_string(kv.first) + " occurs " + std::to_string(kv.second) +
+                                  " times (bond indices occur on exactly two tensors)");
+    *out = guard.release();
+  });
+}
+
+int matnc_network_destroy(matnc_network net) {
+  delete net;
+  return MATNC_OK;
+}
+
+int matnc_plan_create(matnc_network net, const int* pairs, int n_sliced, const int* sliced_ids, int n_open,
+                      const int* open_qubits, int64_t k, const uint64_t* bitstrings, int precision, int max_rank,
+                      int slice_batch, matnc_plan* out) {
+  return guarded([&] {
+    if (!net || !out) fail(MATNC_E_INVALID, "null argument");
+    const Network& N = net->net;
+    const int nt = N.n_tensors;
+    if (nt > 1 && !pairs) fail(MATNC_E_INVALID, "null pairs");
+    if (n_sliced < 0 || n_sliced > 40) fail(MATNC_E_INVALID, "n_sliced must be in 0..40");
+    if (n_sliced > 0 && !sliced_ids) fail(MATNC_E_INVALID, "null sliced_ids");
+    if (n_open < 0 || n_open > N.n_qubits || n_open > 24) fail(MATNC_E_INVALID, "n_open must be in 0..min(n,24)");
+    if (n_open > 0 && !open_qubits) fail(MATNC_E_INVALID, "null open_qubits");
+    if (k < 1 || k > (int64_t)1 << 31 || !bitstrings) fail(MATNC_E_INVALID, "k must be in 1..2^31");
+    if (precision != MATNC_C64 && precision != MATNC_CHALF) fail(MATNC_E_INVALID, "unknown precision");
+    if (precision == MATNC_CHALF && !chalf_available()) fail(MATNC_E_INVALID, "complex-half path not built");
+    if (max_rank < 0) fail(MATNC_E_INVALID, "max_rank must be >= 0");
+    if (slice_batch < 1) fail(MATNC_E_INVALID, "slice_batch must be >= 1");
+    auto h = new matnc_plan_s();
+    std::unique_ptr<matnc_plan_s> guard(h);
+    Plan& P = h->p;
+    P.net = N;
+    P.precision = precision;
+    P.elem_bytes = precision == MATNC_C64 ? 8 : 4;
+    P.max_rank_cap = max_rank;
+    P.batch = slice_batch;
+    // tree
+    std::vector<char> used(2 * nt - 1, 0);
+    for (int j = 0; j < nt - 1; ++j) {
+      const int a = pairs[2 * j], b = pairs[2 * j + 1];
+      if (a < 0 || b < 0 || a >= nt + j || b >= nt + j || a == b || used[a] || used[b])
+        fail(MATNC_E_INVALID, "pairs do not form a contraction tree (step " + std::to_string(j) + ")");
+      used[a] = used[b] = 1;
+      P.pairs.push_back({a, b});
+    }
+    // sliced indices: bond indices, distinct
+    std::unordered_map<int, int> count;
+    for (auto& ix : N.idx)
+      for (int i : ix) ++count[i];
+    std::unordered_map<int, int> outs;
+    for (int q = 0; q < N.n_qubits; ++q) outs[N.out_index[q]] = q;
+    for (int j = 0; j < n_sliced; ++j) {
+      const int i = sliced_ids[j];
+      if (outs.count(i) || count[i] != 2) fail(MATNC_E_INVALID, "sliced id " + std::to_string(i) + " is not a bond");
+      if (std::find(P.sliced.begin(), P.sliced.end(), i) != P.sliced.end())
+        fail(MATNC_E_INVALID, "sliced ids repeat");
+      P.sliced.push_back(i);
+    }
+    uint64_t open_mask = 0;
+    for (int j = 0; j < n_open; ++j) {
+      const int q = open_qubits[j];
+      if (q < 0 || q >= N.n_qubits || ((open_mask >> q) & 1)) fail(MATNC_E_INVALID, "bad or repeated open qubit");
+      open_mask |= 1ull << q;
+    }
+    P.open_qubits.assign(open_qubits, open_qubits + n_open);
+    std::sort(P.open_qubits.begin(), P.open_qubits.end());
+    const uint64_t valid = N.n_qubits == 64 ? ~0ull : ((1ull << N.n_qubits) - 1);
+    P.words.resize((size_t)k);
+    for (int64_t i = 0; i < k; ++i) {
+      if (bitstrings[i] & ~valid) fail(MATNC_E_INVALID, "bitstring " + std::to_string(i) + " sets a bit >= n_qubits");
+      P.words[i] = bitstrings[i] & ~open_mask;
+    }
+    build_structure(P);
+    build_reuse(P);
+    build_steps(P);
+    build_memory(P);
+    *out = guard.release();
+  });
+}
+
+int matnc_plan_info(matnc_plan plan, matnc_plan_info_t* info) {
+  return guarded([&] {
+    if (!plan || !info) fail(MATNC_E_INVALID, "null argument");
+    const Plan& P = plan->p;
+    matnc_plan_info_t I;
+    std::memset(&I, 0, sizeof(I));
+    I.cmac_single = P.cmac_single;
+    I.cmac_multi = P.cmac_multi;
+    I.cmac_invariant = P.cmac_inv;
+    I.cmac_total = P.cmac_total;
+    I.bytes_per_slice = P.bytes_slice;
+    I.bytes_invariant = P.bytes_inv;
+    I.n_slices = (int64_t)1 << P.sliced.size();
+    I.n_amplitudes = (int64_t)P.words.size() << P.open_qubits.size();
+    I.n_unique = P.n_unique;
+    I.max_rank = P.max_rank;
+    I.n_nodes = P.net.n_tensors - 1;
+    I.n_mfma_nodes = P.n_mfma;
+    I.n_launches_per_batch = (int)P.loop.size() + 2;
+    I.workspace_bytes = P.workspace_bytes;
+    I.cache_bytes = P.cache_bytes;
+    *info = I;
+  });
+}
+
+int matnc_plan_set_tensor(matnc_plan plan, int t, const double* data_c128) {
+  return guarded([&] {
+    if (!plan || !data_c128) fail(MATNC_E_INVALID, "null argument");
+    Plan& P = plan->p;
+    if (t < 0 || t >= P.net.n_tensors) fail(MATNC_E_INVALID, "tensor id out of range");
+    const size_t ne = (size_t)1 << P.net.idx[t].size();
+    P.net.data[t].assign(data_c128, data_c128 + 2 * ne);
+    if (P.bound) {
+      const PNode& L = P.nodes[t];
+      std::vector<unsigned char> tmp(L.buf_bytes);
+      fill_leaf_data(P, t, tmp.data());
+      std::memcpy(P.staging.data() + L.off, tmp.data(), L.buf_bytes);
+      hip_check(hipMemcpyAsync(reinterpret_cast<void*>(P.ws + L.off), P.staging.data() + L.off, L.buf_bytes,
+                               hipMemcpyHostToDevice, P.stream),
+                "upload tensor");
+      hip_check(hipStreamSynchronize(P.stream), "upload tensor");
+    }
+    P.inv_valid = false;
+  });
+}
+
+int matnc_plan_bind(matnc_plan plan, void* dev_workspace, size_t bytes, void* hip_stream) {
+  return guarded([&] {
+    if (!plan || !dev_workspace) fail(MATNC_E_INVALID, "null argument");
+    Plan& P = plan->p;
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) fail(MATNC_E_INVALID, "workspace not 256-byte aligned");
+    if (bytes < P.workspace_bytes)
+      fail(MATNC_E_NOMEM, "workspace has " + std::to_string(bytes) + " bytes, plan needs " +
+                              std::to_string(P.workspace_bytes));
+    release_graph(P);
+    P.bound = false;
+    P.ws = reinterpret_cast<uint64_t>(dev_workspace);
+    P.ws_bytes = bytes;
+    P.stream = reinterpret_cast<hipStream_t>(hip_stream);
+    // host image of the static region
+    P.staging.assign(P.static_bytes, 0);
+    const int nt = P.net.n_tensors;
+    for (int v = nt; v < P.n_nodes; ++v) {
+      const PNode& V = P.nodes[v];
+      uint32_t* T = reinterpret_cast<uint32_t*>(P.staging.data() + V.tab_off);
+      const PNode& A = P.nodes[V.swap ? V.b : V.a];
+      const PNode& B = P.nodes[V.swap ? V.a : V.b];
+      fill_table(T + TAB_AM * kTabSize, V.M, A.idx);
+      fill_table(T + TAB_CM * kTabSize, V.M, V.idx);
+      fill_table(T + TAB_BN * kTabSize, V.N, B.idx);
+      fill_table(T + TAB_CN * kTabSize, V.N, V.idx);
+      fill_table(T + TAB_AK * kTabSize, V.K, A.idx);
+      fill_table(T + TAB_BK * kTabSize, V.K, B.idx);
+      std::memcpy(P.staging.data() + V.ga_off, V.ga.data(), V.ga.size() * 4);
+      std::memcpy(P.staging.data() + V.gb_off, V.gb.data(), V.gb.size() * 4);
+    }
+    std::memcpy(P.staging.data() + P.rootmap_off, P.rootmap.data(), P.rootmap.size() * 4);
+    for (int l = 0; l < nt; ++l) fill_leaf_data(P, l, P.staging.data() + P.nodes[l].off);
+    hip_check(hipMemcpyAsync(dev_workspace, P.staging.data(), P.static_bytes, hipMemcpyHostToDevice, P.stream),
+              "upload static region");
+    hip_check(hipStreamSynchronize(P.stream), "upload static region");
+    P.bound = true;
+    P.inv_valid = false;
+    // capture one full slice batch as a graph (not possible on the null stream)
+    if (P.stream != nullptr && !P.loop.empty()) {
+      hip_check(hipStreamBeginCapture(P.stream, hipStreamCaptureModeThreadLocal), "begin capture");
+      try {
+        launch_batch(P, P.batch, P.stream);
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(P.stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      hip_check(hipStreamEndCapture(P.stream, &P.graph), "end capture");
+      hip_check(hipGraphInstantiate(&P.graph_exec, P.graph, nullptr, nullptr, 0), "graph instantiate");
+    }
+  });
+}
+
+int matnc_execute(matnc_plan plan, int64_t slice_begin, int64_t slice_end, double* amps_dev) {
+  return guarded([&] {
+    if (!plan) fail(MATNC_E_INVALID, "null plan");
+    Plan& P = plan->p;
+    if (!P.bound) fail(MATNC_E_STATE, "execute before bind");
+    if (!amps_dev) fail(MATNC_E_INVALID, "null amplitude buffer");
+    const int64_t ns = (int64_t)1 << P.sliced.size();
+    if (slice_begin < 0 || slice_end < slice_begin || slice_end > ns) fail(MATNC_E_INVALID, "bad slice range");
+    hipStream_t st = P.stream;
+    int64_t* sig = reinterpret_cast<int64_t*>(P.ws + P.sigma_off);
+    if (!P.inv_valid) {
+      hip_check(launch_set_i64(sig, 0, st), "set sigma");
+      for (int v : P.prologue) launch_node(P, P.nodes[v], node_desc(P, v, 1), st);
+      P.inv_valid = true;
+    }
+    const OpDesc root = root_desc(P);
+    const int64_t k = (int64_t)P.words.size();
+    const int ob = (int)P.open_qubits.size();
+    for (int64_t s0 = slice_begin; s0 < slice_end; s0 += P.batch) {
+      const int nb = (int)std::min<int64_t>(P.batch, slice_end - s0);
+      hip_check(launch_set_i64(sig, s0, st), "set sigma");
+      if (nb == P.batch && P.graph_exec)
+        hip_check(hipGraphLaunch(P.graph_exec, st), "graph launch");
+      else
+        launch_batch(P, nb, st);
+      hipError_t e = P.precision == MATNC_C64
+                         ? launch_slice_sum(root, P.ws, sig, nb, k, ob, amps_dev, st)
+                         : launch_slice_sum_h(root, P.ws, sig, nb, k, ob, amps_dev, st);
+      hip_check(e, "slice sum");
+    }
+  });
+}
+
+int matnc_xeb(matnc_plan plan, const double* amps_dev, double* xeb_dev) {
+  return guarded([&] {
+    if (!plan || !amps_dev || !xeb_dev) fail(MATNC_E_INVALID, "null argument");
+    Plan& P = plan->p;
+    if (!P.bound) fail(MATNC_E_STATE, "xeb before bind");
+    const int64_t count = (int64_t)P.words.size() << P.open_qubits.size();
+    hip_check(launch_xeb(amps_dev, count, P.net.n_qubits, xeb_dev, P.stream), "xeb");
+  });
+}
+
+int matnc_plan_destroy(matnc_plan plan) {
+  if (plan) {
+    release_graph(plan->p);
+    delete plan;
+  }
+  return MATNC_OK;
+}
+
+int matnc_queue_create(int n_plans, const matnc_plan* plans, matnc_queue* out) {
+  return guarded([&] {
+    if (n_plans < 1 || !plans || !out) fail(MATNC_E_INVALID, "bad queue arguments");
+    auto q = new matnc_queue_s();
+    for (int i = 0; i < n_plans; ++i) {
+      if (!plans[i]) {
+        delete q;
+        fail(MATNC_E_INVALID, "null plan in queue");
+      }
+      q->plans.push_back(plans[i]);
+    }
+    *out = q;
+  });
+}
+
+int matnc_queue_execute(matnc_queue q, double* const* amps_dev, double* xeb_dev) {
+  return guarded([&] {
+    if (!q || !amps_dev || !xeb_dev) fail(MATNC_E_INVALID, "null argument");
+    hipStream_t st = nullptr;
+    for (size_t i = 0; i < q->plans.size(); ++i) {
+      const Plan& P = q->plans[i]->p;
+      if (!P.bound) fail(MATNC_E_STATE, "queue plan " + std::to_string(i) + " is not bound");
+      if (i == 0) st = P.stream;
+      if (P.stream != st) fail(MATNC_E_INVALID, "queue plans must share one stream");
+    }
+    for (size_t i = 0; i < q->plans.size(); ++i) {
+      matnc_plan p = q->plans[i];
+      const int64_t ns = (int64_t)1 << p->p.sliced.size();
+      int rc = matnc_execute(p, 0, ns, amps_dev[i]);
+      if (rc != MATNC_OK) fail(rc, "queue plan " + std::to_string(i) + ": " + g_err);
+      rc = matnc_xeb(p, amps_dev[i], xeb_dev + i);
+      if (rc != MATNC_OK) fail(rc, "queue plan " + std::to_string(i) + ": " + g_err);
+    }
+  });
+}
+
+int matnc_queue_destroy(matnc_queue q) {
+  delete q;
+  return MATNC_OK;
+}
+
+size_t matnc_contract_scratch_bytes(void) { return kAlign + (size_t)TAB_COUNT * kTabSize * 4; }
+
+int matnc_mfma_config_count(void) { return mfma_config_count(); }
+
+int matnc_contract(const void* A, const void* B, void* C, int64_t batch, int nm, int nn, int nk, const int* posA_m,
+                   const int* posA_k, const int* posB_k, const int* posB_n, const int* posC_m, const int* posC_n,
+                   int kernel, void* dev_scratch, size_t scratch_bytes, void* hip_stream) {
+  return guarded([&] {
+    if (!A || !B || !C || !dev_scratch) fail(MATNC_E_INVALID, "null argument");
+    if (batch < 0) fail(MATNC_E_INVALID, "batch must be >= 0");
+    if (nm < 0 || nn < 0 || nk < 0 || nm + nk > 32 || nn + nk > 32 || nm + nn > 32)
+      fail(MATNC_E_INVALID, "ranks must be <= 32");
+    if ((nm && (!posA_m || !posC_m)) || (nn && (!posB_n || !posC_n)) || (nk && (!posA_k || !posB_k)))
+      fail(MATNC_E_INVALID, "null position array");
+    if (reinterpret_cast<uintptr_t>(dev_scratch) % kAlign) fail(MATNC_E_INVALID, "scratch not 256-byte aligned");
+    if (scratch_bytes < matnc_contract_scratch_bytes()) fail(MATNC_E_NOMEM, "scratch too small");
+    auto check_perm = [](std::vector<int> p, const char* what) {
+      std::sort(p.begin(), p.end());
+      for (size_t i = 0; i < p.size(); ++i)
+        if (p[i] != (int)i) fail(MATNC_E_INVALID, std::string(what) + " positions are not a permutation");
+    };
+    std::vector<int> pa, pb, pc;
+    for (int t = 0; t < nm; ++t) pa.push_back(posA_m[t]);
+    for (int t = 0; t < nk; ++t) pa.push_back(posA_k[t]);
+    for (int t = 0; t < nk; ++t) pb.push_back(posB_k[t]);
+    for (int t = 0; t < nn; ++t) pb.push_back(posB_n[t]);
+    for (int t = 0; t < nm; ++t) pc.push_back(posC_m[t]);
+    for (int t = 0; t < nn; ++t) pc.push_back(posC_n[t]);
+    check_perm(pa, "A");
+    check_perm(pb, "B");
+    check_perm(pc, "C");
+    int kind = 0, cfg = -1;
+    if (kernel == -1) {
+      if (nn + nk > 8) {
+        const int order[] = {1, 0, 3, 2};
+        for (int c : order)
+          if (mfma_config_fits(c, nm, nn, nk)) {
+            kind = 1;
+            cfg = c;
+            break;
+          }
+      }
+    } else if (kernel == 0) {
+      kind = 0;
+    } else if (kernel == 1) {
+      for (int c = 0; c < mfma_config_count() && cfg < 0; ++c)
+        if (mfma_config_fits(c, nm, nn, nk)) cfg = c;
+      if (cfg < 0) fail(MATNC_E_INVALID, "no MFMA tile fits this shape");
+      kind = 1;
+    } else if (kernel >= 100 && kernel < 100 + mfma_config_count()) {
+      cfg = kernel - 100;
+      if (!mfma_config_fits(cfg, nm, nn, nk)) fail(MATNC_E_INVALID, "MFMA tile does not fit this shape");
+      kind = 1;
+    } else {
+      fail(MATNC_E_INVALID, "unknown kernel selector");
+    }
+    std::vector<unsigned char> img(matnc_contract_scratch_bytes(), 0);
+    uint32_t* T = reinterpret_cast<uint32_t*>(img.data() + kAlign);
+    auto fill_pos = [](uint32_t* tab, const int* pos, int nbits) {
+      for (int L = 0; L < kTabLevels; ++L)
+        for (int e = 0; e < kTabEntries; ++e) {
+          uint32_t off = 0;
+          for (int t = 0; t < 8; ++t) {
+            const int bit = 8 * L + t;
+            if (((e >> t) & 1) && bit < nbits) off += 1u << pos[bit];
+          }
+          tab[L * kTabEntries + e] = off;
+        }
+    };
+    fill_pos(T + TAB_AM * kTabSize, posA_m, nm);
+    fill_pos(T + TAB_CM * kTabSize, posC_m, nm);
+    fill_pos(T + TAB_BN * kTabSize, posB_n, nn);
+    fill_pos(T + TAB_CN * kTabSize, posC_n, nn);
+    fill_pos(T + TAB_AK * kTabSize, posA_k, nk);
+    fill_pos(T + TAB_BK * kTabSize, posB_k, nk);
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    hip_check(hipMemcpyAsync(dev_scratch, img.data(), img.size(), hipMemcpyHostToDevice, st), "upload tables");
+    hip_check(hipStreamSynchronize(st), "upload tables");
+    const uint64_t base = reinterpret_cast<uint64_t>(dev_scratch);
+    NodeDesc d;
+    std::memset(&d, 0, sizeof(d));
+    auto op = [&](const void* p, int rank) {
+      OpDesc o;
+      std::memset(&o, 0, sizeof(o));
+      o.off = reinterpret_cast<uint64_t>(p);
+      o.inst_bytes = 8ull << rank;
+      o.gmap_off = base + 8;  // a single zero entry
+      o.w_child = 1;
+      o.dep = 1;
+      o.nsv = 1;
+      return o;
+    };
+    d.A = op(A, nm + nk);
+    d.B = op(B, nn + nk);
+    d.c_off = reinterpret_cast<uint64_t>(C);
+    d.c_inst_bytes = 8ull << (nm + nn);
+    d.tab_off = base + kAlign;
+    d.w = 1;
+    d.dep = 1;
+    d.n_inst = batch;
+    d.mbits = nm;
+    d.nbits = nn;
+    d.kbits = nk;
+    const int64_t* sig = reinterpret_cast<const int64_t*>(dev_scratch);
+    hipError_t e = kind == 1 ? launch_mfma(d, cfg, 0, sig, st) : launch_stream(d, 0, sig, st);
+    hip_check(e, "contract launch");
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Host-side plan of a sliced multi-amplitude contraction.
+//
+// A plan is static (main text: the reuse tree fixes contraction pattern,
+// cost and memory before running; Supplementary Sec. III.C): for every node
+// v of the given contraction tree it holds
+//   idx(v)   free indices in storage order (bit 0 = lowest),
+//   O(v)     closed output qubits below v,
+//   keys(v)  the distinct projections of the batch onto O(v), sorted;
+//            w(v) = |keys(v)| is the reuse-tree width at v (Eq. (1)),
+//   ga, gb   gather maps from keys(v) into the children's keys,
+//   dep(v)   whether a sliced index lies below v (slice-dependent),
+// and the memory plan: every intermediate gets a fixed byte range of the
+// caller's workspace for its lifetime in the schedule (invariant nodes once,
+// dependent nodes once per slice batch), found by first-fit over lifetime
+// overlaps.  Slice-invariant tensors consumed by dependent nodes stay for
+// the whole run (the stem cache).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "desc.h"
+
+namespace matnc {
+
+struct Network {
+  int n_tensors = 0;
+  int n_qubits = 0;
+  std::vector<std::vector<int>> idx;      // index ids per tensor (first = most significant)
+  std::vector<std::vector<double>> data;  // interleaved complex128
+  std::vector<int> out_index;             // output index id per qubit
+};
+
+struct PNode {
+  int a = -1, b = -1;        // children (leaf: -1)
+  int parent = -1;
+  std::vector<int> idx;      // free indices, storage order
+  uint64_t omask = 0;
+  bool dep = false;
+  std::vector<uint64_t> keys;
+  std::vector<int32_t> ga, gb;  // per key: index into keys of child A / child B (roles below)
+  // leaf data mapping
+  std::vector<int> sl_bits;      // sigma bits of the sliced indices on this leaf (ascending)
+  std::vector<int> sl_index;     // the sliced index ids, same order
+  // step description (internal nodes)
+  bool swap = false;             // true: operand A is child b
+  int kernel = 0;                // 0 streaming, 1 MFMA
+  int cfg = -1;
+  std::vector<int> M, N, K;      // virtual orders of the three index classes
+  // memory
+  uint64_t inst_elems = 0;
+  uint64_t buf_bytes = 0;        // whole buffer (all instances of a launch)
+  uint64_t off = 0;              // byte offset in workspace
+  uint64_t tab_off = 0, ga_off = 0, gb_off = 0;
+  int time = 0;                  // schedule position
+  int64_t exps_off = 0;          // chalf: byte offset of per-instance exponents
+};
+
+struct Plan {
+  Network net;
+  int n_nodes = 0;               // n_tensors + steps
+  std::vector<std::pair<int, int>> pairs;
+  std::vector<int> sliced;
+  std::vector<int> open_qubits;
+  std::vector<uint64_t> words;   // closed bits only
+  int precision = 0;
+  int max_rank_cap = 0;
+  int batch = 1;
+  int elem_bytes = 8;
+  std::vector<PNode> nodes;
+  std::vector<int32_t> rootmap;
+  uint64_t rootmap_off = 0;
+  uint64_t sigma_off = 0;
+  uint64_t static_bytes = 0;
+  uint64_t workspace_bytes = 0;
+  uint64_t cache_bytes = 0;
+  std::vector<int> prologue, loop;  // node ids in schedule order
+  // costs
+  double cmac_single = 0, cmac_multi = 0, cmac_inv = 0, cmac_total = 0;
+  double bytes_slice = 0, bytes_inv = 0;
+  int max_rank = 0;
+  int n_mfma = 0;
+  int64_t n_unique = 0;
+  // binding
+  bool bound = false;
+  bool inv_valid = false;
+  uint64_t ws = 0;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<unsigned char> staging;  // host image of the static region
+  std::vector<NodeDesc> descs;         // per node (full-batch instance counts)
+};
+
+}  // namespace matnc

@@ -1,0 +1,149 @@
+"""CPU checks of the C ABI: exports, plan figures and error paths.
+
+No kernel runs here: plan creation and its validation are host code.
+"""
+
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2212_04749_amd import api, binding as B, planner as P
+from paper_2212_04749_amd.circuit_tn import build_network
+from workload import CONFIGS, GridSpec, random_circuit, uniform_bitstrings
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "matnc.h")).read()
+    return sorted(set(re.findall(r"\b(matnc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.lib()
+    names = header_functions()
+    assert "matnc_execute" in names and len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert B.matnc_version().startswith("matnc ")
+
+
+def _plan(circ, words, opens=(), cap=None, trials=4, batch=1, precision=0):
+    net = build_network(circ)
+    pl = P.find_plan(net, words, opens, cap, trials=trials)
+    ranks, ids, data = api.network_arrays(net)
+    h = B.matnc_network_create(ranks, ids, data, net.n_qubits, net.output_index)
+    p = B.matnc_plan_create(h, pl.pairs, pl.sliced, list(opens), words, precision, cap or 32, batch)
+    return net, pl, h, p
+
+
+def test_plan_costs_match_planner():
+    w = CONFIGS["C1"]
+    net, pl, h, p = _plan(w.circuit(), w.bitstrings())
+    info = B.matnc_plan_info(p)
+    assert info.cmac_single == pl.costs.S
+    assert info.cmac_multi == pl.costs.S_k
+    assert info.max_rank == pl.costs.max_rank
+    assert info.n_amplitudes == 64
+    B.matnc_plan_destroy(p)
+    B.matnc_network_destroy(h)
+
+
+def test_sliced_costs_and_workspace_growth():
+    circ = random_circuit(GridSpec(3, 4), 8, 5)
+    words = uniform_bitstrings(12, 50, 6)
+    net, pl, h, p1 = _plan(circ, words, cap=7)
+    i1 = B.matnc_plan_info(p1)
+    assert i1.n_slices == 2 ** len(pl.sliced) and i1.max_rank <= 7
+    assert math.isclose(i1.cmac_total, pl.costs.total)
+    p4 = B.matnc_plan_create(h, pl.pairs, pl.sliced, [], words, 0, 7, 4)
+    i4 = B.matnc_plan_info(p4)
+    assert i4.workspace_bytes >= i1.workspace_bytes
+    for p in (p1, p4):
+        B.matnc_plan_destroy(p)
+    B.matnc_network_destroy(h)
+
+
+def test_error_paths():
+    circ = random_circuit(GridSpec(3, 3), 6, 1)
+    words = uniform_bitstrings(9, 10, 2)
+    net = build_network(circ)
+    pl = P.find_plan(net, words, (), None, trials=2)
+    ranks, ids, data = api.network_arrays(net)
+    h = B.matnc_network_create(ranks, ids, data, net.n_qubits, net.output_index)
+    # rank cap too small
+    with pytest.raises(B.MatncError) as e:
+        B.matnc_plan_create(h, pl.pairs, [], [], words, 0, 2, 1)
+    assert e.value.code == B.MATNC_E_RANK
+    # broken tree: a tensor used twice
+    bad = [list(x) for x in pl.pairs]
+    bad[1][0] = bad[0][0]
+    with pytest.raises(B.MatncError) as e:
+        B.matnc_plan_create(h, bad, [], [], words, 0, 32, 1)
+    assert e.value.code == B.MATNC_E_INVALID
+    # bit beyond n_qubits
+    with pytest.raises(B.MatncError) as e:
+        B.matnc_plan_create(h, pl.pairs, [], [], np.array([1 << 9], dtype=np.uint64), 0, 32, 1)
+    assert e.value.code == B.MATNC_E_INVALID
+    # slicing an output index is not allowed
+    with pytest.raises(B.MatncError) as e:
+        B.matnc_plan_create(h, pl.pairs, [net.output_index[0]], [], words, 0, 32, 1)
+    assert e.value.code == B.MATNC_E_INVALID
+    # repeated open qubit
+    with pytest.raises(B.MatncError) as e:
+        B.matnc_plan_create(h, pl.pairs, [], [2, 2], words, 0, 32, 1)
+    assert e.value.code == B.MATNC_E_INVALID
+    # execute before bind
+    p = B.matnc_plan_create(h, pl.pairs, [], [], words, 0, 32, 1)
+    with pytest.raises(B.MatncError) as e:
+        B.matnc_execute(p, 0, 1, 0x1000)
+    assert e.value.code == B.MATNC_E_STATE
+    assert "bind" in B.matnc_last_error()
+    B.matnc_plan_destroy(p)
+    # network: bond index on three tensors
+    with pytest.raises(B.MatncError) as e:
+        B.matnc_network_create([1, 1, 1], [5, 5, 5], np.zeros(12), 1, [7])
+    assert e.value.code == B.MATNC_E_INVALID
+    B.matnc_network_destroy(h)
+
+
+def test_width_law_for_uniform_batches():
+    # Table S3's widths follow the occupancy law E[w] = 2^m (1 - (1 - 2^-m)^k)
+    # of uniform bitstrings (checked to <1% for k = 3e6); the reuse widths of
+    # a uniform batch follow it too
+    k = 3_000_000
+    rows = [(3, 8), (4, 16), (5, 32), (10, 1024), (14, 16384), (16, 65536), (20, 981285),
+            (22, 2123441), (24, 2737958), (26, 2931054), (27, 2965352), (29, 2991260),
+            (30, 2995698), (31, 2997840), (33, 2999468), (34, 2999722)]
+    for m, w in rows:
+        law = 2.0 ** m * (1 - (1 - 2.0 ** -m) ** k)
+        assert abs(law - w) / w < 0.01
+    # same law on our widths: a node with m outputs over a uniform batch
+    words = uniform_bitstrings(30, 4096, 3)
+    for m in (4, 8, 12, 16):
+        mask = np.uint64((1 << m) - 1)
+        wv = np.unique(words & mask).size
+        law = 2.0 ** m * (1 - (1 - 2.0 ** -m) ** 4096)
+        assert abs(wv - law) / law < 0.05
+
+
+def test_contract_pair_batch_counts_complex_elements():
+    # regression: a float32 view holds two floats per complex element, so the
+    # batch must come from the byte size, and mismatched operands are refused
+    # before any launch
+    torch = pytest.importorskip("torch")
+    nm, nn, nk = 4, 2, 2
+    pos = {"posA_m": [0, 1, 2, 3], "posA_k": [4, 5], "posB_k": [0, 1], "posB_n": [2, 3],
+           "posC_m": [0, 1, 2, 3], "posC_n": [4, 5]}
+    A = torch.zeros(3, 2 << (nm + nk), dtype=torch.float32)
+    Bt = torch.zeros(3, 2 << (nn + nk), dtype=torch.float32)
+    C = torch.zeros(3, 2 << (nm + nn), dtype=torch.float32)
+    with pytest.raises(ValueError, match="device"):
+        api.contract_pair(A, Bt, C, pos)          # sizes agree: only the device check fails
+    with pytest.raises(ValueError, match="sizes"):
+        api.contract_pair(A, Bt[:2], C, pos)      # B holds 2 instances, A 3
+    with pytest.raises(ValueError, match="sizes"):
+        api.contract_pair(A[:, :-2], Bt, C, pos)  # A not a whole number of instances
