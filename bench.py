@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""Throughput of the sliced multi-amplitude contraction on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload C2]
+                    [--precision c64|chalf] [--slice-batch B] [--no-cpu-baseline]
+
+One step is one complete pass of the hot path over the workload's batch:
+the slice-invariant (stem) nodes, every slice of the sliced network in
+batches of B slices (gathered branch contractions over the reuse tree), the
+FP64 slice-sum into the amplitudes and the FP64 linear XEB.  Inputs (leaf
+tensors, reuse maps, offset tables) are resident in HBM before the timed
+region; planning and upload are reported separately.
+
+Prints one JSON line: amplitudes/s of the whole job (value), sustained
+complex TFLOP/s, the error of the amplitudes against the stored FP64
+oracle values, a roofline entry for the dominant kernel (HIP-event timings
+of a profiled pass on the plan's stream) and the oracle timed on the host
+cores on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"c64": 157.3, "chalf": 2516.6}  # dense MFMA: FP32, FP16
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4"])
+    p.add_argument("--precision", default="c64", choices=["c64", "chalf"])
+    p.add_argument("--slice-batch", type=int, default=0, help="0 = workload default")
+    p.add_argument("--trials", type=int, default=32, help="order-search candidates")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--profile-out", default="", help="write the per-step profile as JSON")
+    return p.parse_args()
+
+
+def workload_description(name, w, info, spec):
+    g = w.grid
+    shape = f"{g.rows}x{g.cols}" + (f" minus {len(g.removed)} site" if g.removed else "")
+    return {
+        "workload": f"{name}: {shape} grid RQC ({w.n_qubits} qubits), depth {w.depth}, "
+                    f"fSim(pi/2,pi/6), {w.k} uniform bitstrings" +
+                    (f" x 2^{len(w.open_qubits)} open legs" if w.open_qubits else "") +
+                    f", rank cap {spec.cap}, {info.n_slices} slices",
+        "n_qubits": w.n_qubits,
+        "depth": w.depth,
+        "bitstrings": w.k,
+        "open_qubits": len(w.open_qubits),
+        "amplitudes": int(info.n_amplitudes),
+        "rank_cap": spec.cap,
+        "n_slices": int(info.n_slices),
+        "max_rank": int(info.max_rank),
+        "cmac_total": float(info.cmac_total),
+        "kS_over_Sk": float(info.n_unique * info.cmac_single / info.cmac_multi),
+        "plan": spec.method,
+    }
+
+
+def reference_error(name, run, amps_np):
+    """Relative error vs the stored FP64 oracle amplitudes, where stored."""
+    import numpy as np
+    path = {"C2": "c2_subset.json", "C1": None}.get(name)
+    if name == "C1":
+        from oracle import statevector
+        from workload import CONFIGS
+        w = CONFIGS["C1"]
+        ref = statevector.amplitudes(w.circuit(), w.bitstrings())
+        got = amps_np[:, 0]
+    elif path and os.path.exists(os.path.join(ROOT, "tests", "golden", path)):
+        g = json.load(open(os.path.join(ROOT, "tests", "golden", path)))
+        ref = np.array([complex(a, b) for a, b in g["amps"]])
+        got = amps_np[np.array(g["indices"]), 0]
+    else:
+        return None
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    n = run.net.n_qubits
+    xeb_gpu = float(np.ldexp(np.mean(np.abs(got) ** 2), n) - 1)
+    xeb_ref = float(np.ldexp(np.mean(np.abs(ref) ** 2), n) - 1)
+    return {"rel_err": err, "samples": int(len(ref)), "xeb_abs_err_on_samples": abs(xeb_gpu - xeb_ref)}
+
+
+def roofline(run, precision, n_batches, nb_last):
+    """Aggregate a profiled pass per kernel; the dominant kernel's algorithmic
+    flops (MFMA) or bytes (streaming) per launch over its mean launch time."""
+    prof = run.profile(0, min(run.slice_batch, run.n_slices))
+    per = {}
+    for (ms, kid, cmac, by), dep in zip(prof, run.step_dep()):
+        if ms < 0:
+            continue
+        reps = n_batches if dep else 1
+        e = per.setdefault(kid, {"ms": 0.0, "cmac": 0.0, "bytes": 0.0, "launches": 0})
+        e["ms"] += ms * reps
+        e["cmac"] += cmac * reps
+        e["bytes"] += by * reps
+        e["launches"] += reps
+    kid = max(per, key=lambda k: per[k]["ms"])
+    e = per[kid]
+    t = e["ms"] / 1e3
+    if kid >= 100:
+        achieved = 8 * e["cmac"] / t / 1e12
+        r = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s"}
+    else:
+        achieved = e["bytes"] / t / 1e9
+        r = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    r["frac"] = r["achieved"] / r["peak"]
+    r["traffic"] = None
+    r["kernel"] = f"mfma cfg {kid - 100}" if kid >= 100 else "streaming"
+    r["launches"] = e["launches"]
+    r["mean_launch_ms"] = e["ms"] / e["launches"]
+    r["share_of_step"] = e["ms"] / sum(v["ms"] for v in per.values())
+    return r, per
+
+
+def cpu_baseline(name, w):
+    """The oracle (plain-C FP64 state vector) on a bounded sample: the set-up
+    and the first G_s gates are timed and the full-circuit time is
+    extrapolated linearly in the gate count; the oracle's amplitudes/s for
+    this workload is k over that time."""
+    from oracle import sv_native
+    from oracle.circuit import gate_list
+    circ, words = w.circuit(), w.bitstrings()
+    if w.n_qubits > 30:
+        return None
+    n, glist = gate_list(circ)
+    t0 = time.perf_counter()
+    sv_native.amplitudes(circ, words, max_gates=0)
+    t_setup = time.perf_counter() - t0
+    gs = min(len(glist), 60)
+    t0 = time.perf_counter()
+    sv_native.amplitudes(circ, words, max_gates=gs)
+    t_sample = time.perf_counter() - t0
+    per_gate = max(t_sample - t_setup, 1e-9) / gs
+    t_full = t_setup + per_gate * len(glist)
+    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    return {"value": w.k / t_full, "unit": "amplitudes/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 state vector (oracle/sv.c) of the same {w.n_qubits}-qubit circuit: set-up plus the "
+                      f"first {gs} of {len(glist)} gates timed ({t_sample:.1f} s), full run extrapolated to "
+                      f"{t_full:.1f} s for all {w.k} bitstrings"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU slice sharding is not built",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    from paper_2212_04749_amd import api, planner
+    from paper_2212_04749_amd.circuit_tn import build_network
+    from workload import CONFIGS
+
+    name = args.workload
+    w = CONFIGS[name]
+    batch = args.slice_batch or {"C1": 1, "C2": 4, "C3": 8, "C4": 1}[name]
+    circ, words = w.circuit(), w.bitstrings()
+    t0 = time.perf_counter()
+    net = build_network(circ)
+    cap = w.cap if w.cap is not None else 32
+    plan = planner.find_plan(net, words, w.open_qubits, w.cap, seed=0, trials=args.trials,
+                             exact_slices=w.n_slices_target.bit_length() - 1 if w.n_slices_target else None)
+    spec = api.PlanSpec(plan.pairs, plan.sliced, tuple(w.open_qubits), cap, plan.method)
+    t_plan = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    run = api.Contraction(net, spec, words, precision=args.precision, slice_batch=batch)
+    torch.cuda.synchronize()
+    t_bind = time.perf_counter() - t0
+    info = run.info
+    log(f"plan {t_plan:.2f}s bind {t_bind:.2f}s workspace {info.workspace_bytes / 2**30:.2f} GiB "
+        f"slices {info.n_slices} cmac_total {info.cmac_total:.3e}")
+
+    amps = run.new_amplitudes()
+    xeb_out = None
+
+    def step():
+        nonlocal xeb_out
+        run.reset_cache()
+        with torch.cuda.stream(run.stream):
+            amps.zero_()
+        run.execute(amps)
+        xeb_out = run.xeb_dev(amps)
+
+    for i in range(args.warmup):
+        step()
+        run.synchronize()
+        log(f"warmup {i} done")
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(run.stream)
+    for i in range(args.steps):
+        step()
+    ev1.record(run.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.2f} ms/step (wall {wall / args.steps * 1e3:.2f} ms/step)")
+
+    amps_np = amps.cpu().numpy()
+    amps_c = amps_np[..., 0] + 1j * amps_np[..., 1]
+    xeb = float(xeb_out.cpu().item())
+    err = reference_error(name, run, amps_c)
+    n_batches = -(-run.n_slices // batch)
+    roof, per = roofline(run, args.precision, n_batches, run.n_slices - (n_batches - 1) * batch)
+    if args.profile_out:
+        with open(args.profile_out, "w") as f:
+            json.dump({"per_kernel": {str(k): v for k, v in per.items()}}, f, indent=1)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        try:
+            cpu = cpu_baseline(name, w)
+        except MemoryError:
+            cpu = None
+    secs = ms_step / 1e3
+    out = {
+        "metric": "sustained complex TFLOP/s + amplitudes/sec per slice-batch at stated err vs FP64",
+        "value": info.n_amplitudes / secs,
+        "unit": "amplitudes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "complex64" if args.precision == "c64" else "complex-half",
+        "data": "synthetic",
+        "complex_tflops": 8 * info.cmac_total / secs / 1e12,
+        "mfma_peak_frac": 8 * info.cmac_total / secs / 1e12 / PEAK_TFLOPS[args.precision],
+        "xeb": xeb,
+        "error_vs_fp64": err,
+        "plan_s": t_plan,
+        "bind_s": t_bind,
+        "config": workload_description(name, w, info, spec) | {"slice_batch": batch, "precision": args.precision},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    run.close()
+
+
+if __name__ == "__main__":
+    main()

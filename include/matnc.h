@@ -178,6 +178,31 @@ int matnc_xeb(matnc_plan plan, const double *amps_dev, double *xeb_dev);
 int matnc_plan_destroy(matnc_plan plan);
 
 /*
+ * matnc_plan_reset_cache -- drop the slice-invariant tensors (stem cache)
+ * so that the next matnc_execute recomputes them; used to time a complete
+ * pass.  No device work is queued.  Errors: MATNC_E_INVALID (null plan).
+ */
+int matnc_plan_reset_cache(matnc_plan plan);
+
+/*
+ * matnc_plan_profile -- diagnostic pass: recompute the slice-invariant
+ * nodes, then contract one slice batch of nb slices (1 <= nb <= slice_batch)
+ * starting at slice_begin, with a HIP event pair around every node's launch
+ * on the bound stream; waits for the stream.  For step j (0 <= j <
+ * n_tensors - 1) it writes
+ *   time_ms[j]  elapsed time of that launch (-1 if the node has no work),
+ *   kernel[j]   0 = streaming kernel, 100 + c = MFMA tile configuration c,
+ *   cmac[j]     algorithmic complex MACs of the launch (w * instances * 2^(m+n+k)),
+ *   bytes[j]    algorithmic HBM bytes of the launch (each output instance
+ *               written once, each distinct operand instance read once).
+ * Arrays are caller-owned host memory of n_tensors - 1 entries.  The
+ * amplitude buffers are not touched.  Errors: MATNC_E_STATE, MATNC_E_INVALID,
+ * MATNC_E_HIP.
+ */
+int matnc_plan_profile(matnc_plan plan, int64_t slice_begin, int nb, float *time_ms, int *kernel,
+                       double *cmac, double *bytes);
+
+/*
  * Uneven batches: several bound plans (each with its own workspace and
  * circuit) executed over all of their slices as one queue, with one FP64
  * amplitude buffer and one XEB slot per plan.

@@ -82,6 +82,7 @@ class Contraction:
             self.close()
             raise
         self.n_open = len(spec.open_qubits)
+        self.slice_batch = slice_batch
         self.k = len(self.words)
         self.n_slices = int(self.info.n_slices)
 
@@ -146,6 +147,22 @@ class Contraction:
         out = self.xeb_dev(amps)
         self.synchronize()
         return float(out.cpu().item())
+
+    def step_dep(self):
+        """Per contraction step: True if a sliced index lies below it (runs once per slice)."""
+        sl = set(self.spec.sliced)
+        dep = [any(i in sl for i in ix) for ix in self.net.indices]
+        for a, b in self.spec.pairs:
+            dep.append(dep[a] or dep[b])
+        return dep[len(self.net.indices):]
+
+    def reset_cache(self) -> None:
+        B.matnc_plan_reset_cache(self._plan)
+
+    def profile(self, slice_begin: int = 0, nb: Optional[int] = None):
+        """Per contraction step: (time_ms, kernel id, cmac, bytes) of one batch."""
+        nb = nb or min(self.slice_batch, self.n_slices - slice_begin)
+        return B.matnc_plan_profile(self._plan, slice_begin, nb, len(self.net.tensors) - 1)
 
     def set_tensor(self, t: int, data: np.ndarray) -> None:
         B.matnc_plan_set_tensor(self._plan, t, tensor_array(data))

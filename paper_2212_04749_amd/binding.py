@@ -62,7 +62,7 @@ EXPORTS = [
     "matnc_plan_create", "matnc_plan_info", "matnc_plan_set_tensor", "matnc_plan_bind",
     "matnc_execute", "matnc_xeb", "matnc_plan_destroy", "matnc_queue_create",
     "matnc_queue_execute", "matnc_queue_destroy", "matnc_contract_scratch_bytes",
-    "matnc_mfma_config_count", "matnc_contract",
+    "matnc_mfma_config_count", "matnc_contract", "matnc_plan_reset_cache", "matnc_plan_profile",
 ]
 
 
@@ -92,6 +92,9 @@ def lib():
     L.matnc_queue_create.argtypes = [c_int, POINTER(c_void_p), POINTER(c_void_p)]
     L.matnc_queue_execute.argtypes = [c_void_p, POINTER(c_void_p), c_void_p]
     L.matnc_queue_destroy.argtypes = [c_void_p]
+    L.matnc_plan_reset_cache.argtypes = [c_void_p]
+    L.matnc_plan_profile.argtypes = [c_void_p, c_int64, c_int, POINTER(ctypes.c_float), POINTER(c_int),
+                                     POINTER(c_double), POINTER(c_double)]
     L.matnc_contract_scratch_bytes.restype = c_size_t
     L.matnc_contract_scratch_bytes.argtypes = []
     L.matnc_mfma_config_count.restype = c_int
@@ -220,3 +223,17 @@ def matnc_contract(A: int, B: int, C: int, batch: int, posA_m, posA_k, posB_k, p
                                len(posA_k), int_array(posA_m), int_array(posA_k), int_array(posB_k),
                                int_array(posB_n), int_array(posC_m), int_array(posC_n), int(kernel),
                                c_void_p(scratch), c_size_t(scratch_bytes), c_void_p(hip_stream)))
+
+
+def matnc_plan_reset_cache(plan: int) -> None:
+    check(lib().matnc_plan_reset_cache(c_void_p(plan)))
+
+
+def matnc_plan_profile(plan: int, slice_begin: int, nb: int, n_steps: int):
+    """Per-step (time_ms, kernel id, cmac, bytes) of one profiled batch."""
+    t = (ctypes.c_float * max(1, n_steps))()
+    k = (c_int * max(1, n_steps))()
+    c = (c_double * max(1, n_steps))()
+    b = (c_double * max(1, n_steps))()
+    check(lib().matnc_plan_profile(c_void_p(plan), c_int64(slice_begin), int(nb), t, k, c, b))
+    return [(t[j], k[j], c[j], b[j]) for j in range(n_steps)]

@@ -31,6 +31,7 @@ struct OpDesc {
   uint64_t off;         // byte offset of instance 0 in the workspace
   uint64_t inst_bytes;  // bytes per instance
   uint64_t gmap_off;    // byte offset of the int32 gather map (one entry per j)
+  uint64_t scale_off;   // complex-half: byte offset of the {int32 e, uint32 max} pair of instance 0
   int32_t w_child;      // instances per slice of the operand
   int32_t dep;          // 1: operand instances repeat per slice
   int32_t nsv;          // leaf: 2^nsb slice variants per key; else 1
@@ -43,13 +44,20 @@ struct NodeDesc {
   uint64_t c_off;        // byte offset of output instance 0
   uint64_t c_inst_bytes; // bytes per output instance
   uint64_t tab_off;      // byte offset of the TAB_COUNT x kTabSize uint32 tables
-  uint64_t scale_off;    // chalf: byte offset of int32 exponents (A, B, C arrays) -- unused for c64
+  uint64_t c_scale_off;  // complex-half: byte offset of the output's {e, max} pairs
   int64_t n_inst;        // instances in this launch = w * (dep ? batch : 1)
   int32_t w;             // reuse-tree width w(v)
   int32_t dep;           // output instances repeat per slice
   int32_t mbits, nbits, kbits;
-  int32_t a_scale_off_idx, b_scale_off_idx;  // chalf exponent bookkeeping
   int32_t pad;
+};
+
+// Complex-half scaling of one stored instance: true value = stored half *
+// 2^e; mx = largest |re| or |im| of the stored halves (float bits, so that
+// unsigned atomicMax orders it).
+struct HalfScale {
+  int32_t e;
+  uint32_t mx;
 };
 
 __host__ __device__ inline int64_t sub_index(const OpDesc& o, int64_t sigma) {

@@ -782,6 +782,75 @@ int matnc_plan_destroy(matnc_plan plan) {
   return MATNC_OK;
 }
 
+int matnc_plan_reset_cache(matnc_plan plan) {
+  return guarded([&] {
+    if (!plan) fail(MATNC_E_INVALID, "null plan");
+    plan->p.inv_valid = false;
+  });
+}
+
+int matnc_plan_profile(matnc_plan plan, int64_t slice_begin, int nb, float* time_ms, int* kernel, double* cmac,
+                       double* bytes) {
+  return guarded([&] {
+    if (!plan || !time_ms || !kernel || !cmac || !bytes) fail(MATNC_E_INVALID, "null argument");
+    Plan& P = plan->p;
+    if (!P.bound) fail(MATNC_E_STATE, "profile before bind");
+    const int64_t ns = (int64_t)1 << P.sliced.size();
+    if (nb < 1 || nb > P.batch || slice_begin < 0 || slice_begin + nb > ns) fail(MATNC_E_INVALID, "bad batch");
+    const int nt = P.net.n_tensors;
+    const int steps = nt - 1;
+    std::vector<int> order(P.prologue);
+    order.insert(order.end(), P.loop.begin(), P.loop.end());
+    std::vector<hipEvent_t> ev(2 * order.size(), nullptr);
+    struct EvGuard {
+      std::vector<hipEvent_t>& e;
+      ~EvGuard() {
+        for (auto x : e)
+          if (x) (void)hipEventDestroy(x);
+      }
+    } eg{ev};
+    for (auto& e : ev) hip_check(hipEventCreate(&e), "event create");
+    hipStream_t st = P.stream;
+    int64_t* sig = reinterpret_cast<int64_t*>(P.ws + P.sigma_off);
+    hip_check(launch_set_i64(sig, 0, st), "set sigma");
+    for (size_t i = 0; i < order.size(); ++i) {
+      const int v = order[i];
+      const PNode& V = P.nodes[v];
+      if (i == P.prologue.size()) hip_check(launch_set_i64(sig, slice_begin, st), "set sigma");
+      const NodeDesc d = node_desc(P, v, V.dep ? nb : 1);
+      hip_check(hipEventRecord(ev[2 * i], st), "event record");
+      launch_node(P, V, d, st);
+      hip_check(hipEventRecord(ev[2 * i + 1], st), "event record");
+    }
+    hip_check(hipStreamSynchronize(st), "profile sync");
+    P.inv_valid = true;
+    for (int j = 0; j < steps; ++j) {
+      time_ms[j] = -1.f;
+      kernel[j] = 0;
+      cmac[j] = 0;
+      bytes[j] = 0;
+    }
+    const double eb = P.elem_bytes;
+    for (size_t i = 0; i < order.size(); ++i) {
+      const int v = order[i];
+      const PNode& V = P.nodes[v];
+      const int j = v - nt;
+      float ms = 0.f;
+      hip_check(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]), "event time");
+      time_ms[j] = ms;
+      kernel[j] = V.kernel == 1 ? 100 + V.cfg : 0;
+      const double inst = (double)V.keys.size() * (V.dep ? nb : 1);
+      cmac[j] = inst * std::ldexp(1.0, (int)(V.M.size() + V.N.size() + V.K.size()));
+      const PNode& A = P.nodes[V.swap ? V.b : V.a];
+      const PNode& B = P.nodes[V.swap ? V.a : V.b];
+      const double ia = (double)A.keys.size() * (A.dep ? (V.dep ? nb : 1) : 1);
+      const double ib = (double)B.keys.size() * (B.dep ? (V.dep ? nb : 1) : 1);
+      bytes[j] = eb * (inst * std::ldexp(1.0, (int)V.idx.size()) + ia * std::ldexp(1.0, (int)A.idx.size()) +
+                       ib * std::ldexp(1.0, (int)B.idx.size()));
+    }
+  });
+}
+
 int matnc_queue_create(int n_plans, const matnc_plan* plans, matnc_queue* out) {
   return guarded([&] {
     if (n_plans < 1 || !plans || !out) fail(MATNC_E_INVALID, "bad queue arguments");

@@ -363,11 +363,41 @@ class Plan:
     method: str
 
 
+def refine(st: Structure, plan: Plan, words: np.ndarray, cap: Optional[int],
+           exact_slices: Optional[int] = None, rounds: int = 4) -> Plan:
+    """Alternate subtree reconfiguration (sizes 6, 8, 10) with re-slicing
+    until the total cost stops falling."""
+    best = plan
+    pairs = list(plan.pairs)
+    sliced = list(plan.sliced)
+    for _ in range(rounds):
+        sl = sum(1 << i for i in sliced)
+        for size in (6, 8, 10):
+            pairs = reconfigure(st, pairs, words, cap, sl, size=size, passes=4)
+        tree = build_tree(st, pairs)
+        w = widths(tree, words)
+        c = costs(st, build_tree(st, pairs, sl), w, sl)
+        cand = Plan(pairs, sliced, c, w, best.method + "+reconf")
+        try:
+            s2, c2 = slice_to_cap(st, pairs, w, cap, min_slices=exact_slices or 0)
+            if (exact_slices is None or len(s2) == exact_slices) and c2.total < c.total:
+                cand = Plan(pairs, s2, c2, w, best.method + "+reconf")
+        except ValueError:
+            pass
+        if cand.costs.total < best.costs.total * (1 - 1e-6):
+            best = cand
+            pairs, sliced = list(cand.pairs), list(cand.sliced)
+        else:
+            break
+    return best
+
+
 def find_plan(net: TensorNetwork, words: np.ndarray, open_qubits: Sequence[int] = (),
               cap: Optional[int] = None, seed: int = 0, trials: int = 64,
               min_slices: int = 0, exact_slices: Optional[int] = None,
-              include_greedy: bool = True) -> Plan:
-    """Search candidate orders; slice each to the cap; keep the cheapest."""
+              include_greedy: bool = True, refine_top: int = 3) -> Plan:
+    """Search candidate orders; slice each to the cap; refine the cheapest
+    few by subtree reconfiguration; keep the cheapest."""
     st = Structure.from_network(net, open_qubits)
     words = np.asarray(words, dtype=np.uint64)
     k_eff = int(np.unique(words).size)
@@ -380,7 +410,7 @@ def find_plan(net: TensorNetwork, words: np.ndarray, open_qubits: Sequence[int] 
         temp = float(rng.uniform(0.0, 1.0))
         temp2 = float(rng.uniform(0.0, 0.5)) if t % 2 else 0.0
         candidates.append((f"stem-branch[{t}]", stem_branch_pairs(st, k_eff, rng, alpha, temp, temp2)))
-    best: Optional[Plan] = None
+    scored = []
     for name, pairs in candidates:
         tree = build_tree(st, pairs)
         w = widths(tree, words)
@@ -392,8 +422,186 @@ def find_plan(net: TensorNetwork, words: np.ndarray, open_qubits: Sequence[int] 
         # indices to reach the cap keeps its real count
         miss = 0 if exact_slices is None else abs(len(sliced) - exact_slices)
         key = (miss, c.total, c.max_rank)
-        if best is None or key < best[0]:
-            best = (key, Plan(list(pairs), sliced, c, w, name))
-    if best is None:
+        scored.append((key, Plan(list(pairs), sliced, c, w, name)))
+    if not scored:
         raise ValueError("no plan meets the cap")
-    return best[1]
+    scored.sort(key=lambda x: x[0])
+    out = []
+    for key, pl in scored[:max(1, refine_top)]:
+        r = refine(st, pl, words, cap, exact_slices) if refine_top > 0 else pl
+        miss = 0 if exact_slices is None else abs(len(r.sliced) - exact_slices)
+        out.append(((miss, r.costs.total, r.costs.max_rank), r))
+    out.sort(key=lambda x: x[0])
+    return out[0][1]
+
+
+# --------------------------------------------------------------------------
+# local refinement: subtree reconfiguration
+#
+# Take a subtree whose frontier is m <= 8 sub-trees, and replace its internal
+# shape by the cheapest binary tree over that frontier, found by dynamic
+# programming over subsets (3^m work).  The cost of a node is the
+# multi-amplitude step cost w(v) * CMAC(v) (Eq. (1)), multiplied by the
+# number of slices when a sliced index lies below it; a node over the rank
+# cap costs infinity.  Repeating this over all nodes is a local search that
+# never increases the total cost.
+
+
+class _Tree:
+    def __init__(self, st: Structure, pairs, sliced_mask: int, words: np.ndarray):
+        n = st.n_tensors
+        self.n = n
+        self.st = st
+        self.children = {}
+        self.masks = [m & ~sliced_mask for m in st.leaf_masks]
+        self.outs = list(st.leaf_outputs)
+        self.dep = [bool(m & sliced_mask) for m in st.leaf_masks]
+        self.nsl = bin(sliced_mask).count("1")
+        self.words = words
+        self._w = {}
+        for j, (a, b) in enumerate(pairs):
+            v = n + j
+            self.children[v] = (a, b)
+            self.masks.append(self.masks[a] ^ self.masks[b])
+            self.outs.append(self.outs[a] | self.outs[b])
+            self.dep.append(self.dep[a] or self.dep[b])
+        self.root = n + len(pairs) - 1 if pairs else 0
+
+    def width(self, o: int) -> int:
+        if o == 0:
+            return 1
+        w = self._w.get(o)
+        if w is None:
+            w = int(np.unique(self.words & np.uint64(o)).size)
+            self._w[o] = w
+        return w
+
+    def new_node(self, a, b):
+        v = len(self.masks)
+        self.children[v] = (a, b)
+        self.masks.append(self.masks[a] ^ self.masks[b])
+        self.outs.append(self.outs[a] | self.outs[b])
+        self.dep.append(self.dep[a] or self.dep[b])
+        return v
+
+    def to_pairs(self):
+        pairs = []
+        ids = {t: t for t in range(self.n)}
+
+        def visit(v):
+            if v < self.n:
+                return ids[v]
+            a, b = self.children[v]
+            x, y = visit(a), visit(b)
+            pairs.append((x, y))
+            return self.n + len(pairs) - 1
+
+        import sys
+        sys.setrecursionlimit(max(10000, 4 * self.n))
+        visit(self.root)
+        return pairs
+
+
+def _optimal_subtree(T: _Tree, frontier, cap):
+    m = len(frontier)
+    full = (1 << m) - 1
+    fm = [T.masks[f] for f in frontier]
+    fo = [T.outs[f] for f in frontier]
+    fd = [T.dep[f] for f in frontier]
+    mask = [0] * (1 << m)
+    outs = [0] * (1 << m)
+    dep = [False] * (1 << m)
+    for s in range(1, 1 << m):
+        low = s & -s
+        i = low.bit_length() - 1
+        rest = s ^ low
+        mask[s] = mask[rest] ^ fm[i]
+        outs[s] = outs[rest] | fo[i]
+        dep[s] = dep[rest] or fd[i]
+    mult = 2.0 ** T.nsl
+    INF = float("inf")
+    best = [INF] * (1 << m)
+    split = [0] * (1 << m)
+    for i in range(m):
+        best[1 << i] = 0.0
+    for s in range(1, 1 << m):
+        if s & (s - 1) == 0:
+            continue
+        if cap is not None and bin(mask[s]).count("1") > cap:
+            continue
+        w = T.width(outs[s])
+        f = w * (mult if dep[s] else 1.0)
+        # enumerate splits with the lowest set bit in y to halve the work
+        low = s & -s
+        sub = (s - 1) & s
+        b = INF
+        bs = 0
+        while sub:
+            if sub & low:
+                y, z = sub, s ^ sub
+                if best[y] < INF and best[z] < INF:
+                    c = best[y] + best[z] + f * 2.0 ** bin(mask[y] | mask[z]).count("1")
+                    if c < b:
+                        b, bs = c, y
+            sub = (sub - 1) & s
+        best[s] = b
+        split[s] = bs
+    return best[full], split
+
+
+def _subtree_cost(T: _Tree, v, frontier_set):
+    if v in frontier_set:
+        return 0.0
+    a, b = T.children[v]
+    mult = 2.0 ** T.nsl if T.dep[v] else 1.0
+    c = T.width(T.outs[v]) * mult * 2.0 ** bin(T.masks[a] | T.masks[b]).count("1")
+    return c + _subtree_cost(T, a, frontier_set) + _subtree_cost(T, b, frontier_set)
+
+
+def reconfigure(st: Structure, pairs, words, cap: Optional[int], sliced_mask: int = 0,
+                size: int = 8, passes: int = 2) -> List[Tuple[int, int]]:
+    """Local search over subtrees of ``size`` frontier nodes (see above)."""
+    words = np.asarray(words, dtype=np.uint64)
+    T = _Tree(st, pairs, sliced_mask, words)
+    for _ in range(passes):
+        changed = False
+        # visit internal nodes from the root down
+        order = []
+        stack = [T.root]
+        while stack:
+            v = stack.pop()
+            if v >= T.n:
+                order.append(v)
+                stack.extend(T.children[v])
+        for v in order:
+            if v not in T.children:
+                continue
+            # grow the frontier by expanding the most expensive internal node
+            frontier = list(T.children[v])
+            while len(frontier) < size:
+                cand = [f for f in frontier if f >= T.n]
+                if not cand:
+                    break
+                f = max(cand, key=lambda x: (bin(T.masks[x]).count("1"), x))
+                frontier.remove(f)
+                frontier.extend(T.children[f])
+            if len(frontier) < 3:
+                continue
+            old = _subtree_cost(T, v, set(frontier))
+            new, split = _optimal_subtree(T, frontier, cap)
+            if new < old * (1 - 1e-9):
+                def build(s):
+                    if s & (s - 1) == 0:
+                        return frontier[s.bit_length() - 1]
+                    y = split[s]
+                    return T.new_node(build(y), build(s ^ y))
+                a_s = split[(1 << len(frontier)) - 1]
+                full = (1 << len(frontier)) - 1
+                na, nb = build(a_s), build(full ^ a_s)
+                # rewire v in place so that its parent keeps pointing at it
+                T.children[v] = (na, nb)
+                T.masks[v] = T.masks[na] ^ T.masks[nb]
+                changed = True
+        if not changed:
+            break
+    return T.to_pairs()

@@ -131,3 +131,24 @@ def test_permutation_circuit_c2_size():
     ref = closed_forms.permutation_amplitudes(circ, words)
     assert rel_err(got, ref) <= 1e-5
     run.close()
+
+
+def test_c2_full_config_against_stored_oracle():
+    """5x6 depth-12, 4096 bitstrings, cap 28 (all slices): the seeded
+    256-bitstring subset against the stored FP64 state-vector amplitudes."""
+    import json
+    import os
+    require_gpu()
+    w = CONFIGS["C2"]
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_subset.json")))
+    circ, words = w.circuit(), w.bitstrings()
+    idx = np.array(g["indices"])
+    assert [str(int(x)) for x in words[idx]] == g["words"]
+    ref = np.array([complex(a, b) for a, b in g["amps"]])
+    say("C2 full config, cap 28, k=4096, batch 4")
+    run = contraction(circ, words, cap=28, batch=4, trials=4)
+    got = run.amplitudes()[idx]
+    assert rel_err(got, ref) <= 1e-5
+    n = 30
+    assert abs((np.ldexp(np.mean(np.abs(got) ** 2), n) - 1) - (np.ldexp(np.mean(np.abs(ref) ** 2), n) - 1)) <= 1e-4
+    run.close()
