@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmatnc.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["matnc.cpp", "kernels_c64.hip", "kernels_chalf.hip"]
+SOURCES = ["matnc.cpp", "kernels_stream.hip", "kernels_c64.hip", "kernels_chalf.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

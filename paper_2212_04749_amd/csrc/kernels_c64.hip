@@ -1,10 +1,8 @@
 // complex64 kernels of the contraction path (gfx950).
 //
-//  * k_stream_*: one pairwise step C[m, n] = sum_k A[m, k] B[k, n] whose small
-//    operand B has at most 2^8 elements: HBM-bound, one lane per m, lanes
-//    walking the lowest storage bits of A and C, B read with block-uniform
-//    addresses (scalar loads) when a block stays inside one instance.
-//  * k_mfma_*: the same step when N and K are large: a complex GEMM on
+//  * k_mfma: one pairwise step C[m, n] = sum_k A[m, k] B[k, n] with large N
+//    and K (the streaming kernels of kernels_stream.hip take the rest): a
+//    complex GEMM on
 //    v_mfma_f32_32x32x2f32 through the real embedding
 //    [Ar Ai] x [[Br, Bi], [-Bi, Br]] = [Cr Ci] (8 real flops per complex
 //    MAC, so MFMA flops equal complex flops), LDS-staged, double-buffered
@@ -22,120 +20,6 @@
 #include "kernels.h"
 
 namespace matnc {
-
-// ---------------------------------------------------------------------------
-// streaming kernels
-
-// Blocks of 256 lanes cover 256 consecutive m of one instance (mbits >= 8).
-template <int KB, int NB>
-__global__ __launch_bounds__(256) void k_stream_wide(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
-  const uint32_t* __restrict__ tab = reinterpret_cast<const uint32_t*>(ws + d.tab_off);
-  const int32_t* __restrict__ glA = reinterpret_cast<const int32_t*>(ws + d.A.gmap_off);
-  const int32_t* __restrict__ glB = reinterpret_cast<const int32_t*>(ws + d.B.gmap_off);
-  const int64_t bpi = (int64_t)1 << (d.mbits - 8);
-  const int64_t nblk = d.n_inst * bpi;
-  const int64_t sigma0 = sig[0];
-  const uint32_t lo = threadIdx.x;
-  const uint32_t oa_lo = tab[TAB_AM * kTabSize + lo];
-  const uint32_t oc_lo = tab[TAB_CM * kTabSize + lo];
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-    const int64_t inst = blk >> (d.mbits - 8);
-    const uint32_t hi = (uint32_t)(blk & (bpi - 1));
-    const int64_t s = d.dep ? inst / d.w : 0;
-    const int64_t j = d.dep ? inst - s * d.w : inst;
-    const int64_t sigma = sigma0 + s;
-    const int64_t ai = operand_instance(d.A, glA, j, s, sigma);
-    const int64_t bi = operand_instance(d.B, glB, j, s, sigma);
-    const float2* __restrict__ pa = reinterpret_cast<const float2*>(ws + d.A.off + ai * d.A.inst_bytes);
-    const float2* __restrict__ pb = reinterpret_cast<const float2*>(ws + d.B.off + bi * d.B.inst_bytes);
-    float2* __restrict__ pc = reinterpret_cast<float2*>(ws + d.c_off + inst * d.c_inst_bytes);
-    const uint32_t* TA = tab + TAB_AM * kTabSize;
-    const uint32_t* TC = tab + TAB_CM * kTabSize;
-    const uint32_t oa = oa_lo + TA[256 + (hi & 255u)] + TA[512 + ((hi >> 8) & 255u)] + TA[768 + (hi >> 16)];
-    const uint32_t oc = oc_lo + TC[256 + (hi & 255u)] + TC[512 + ((hi >> 8) & 255u)] + TC[768 + (hi >> 16)];
-    float2 a[KB];
-#pragma unroll
-    for (int k = 0; k < KB; ++k) a[k] = pa[oa + tab[TAB_AK * kTabSize + k]];
-#pragma unroll
-    for (int n = 0; n < NB; ++n) {
-      float2 c = make_float2(0.f, 0.f);
-      const uint32_t bn = tab[TAB_BN * kTabSize + n];
-#pragma unroll
-      for (int k = 0; k < KB; ++k) cmac(c, a[k], pb[bn + tab[TAB_BK * kTabSize + k]]);
-      pc[oc + tab[TAB_CN * kTabSize + n]] = c;
-    }
-  }
-}
-
-// One lane per (instance, m) with m < 2^mbits < 256.
-template <int KB, int NB>
-__global__ __launch_bounds__(256) void k_stream_narrow(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
-  const uint32_t* __restrict__ tab = reinterpret_cast<const uint32_t*>(ws + d.tab_off);
-  const int32_t* __restrict__ glA = reinterpret_cast<const int32_t*>(ws + d.A.gmap_off);
-  const int32_t* __restrict__ glB = reinterpret_cast<const int32_t*>(ws + d.B.gmap_off);
-  const int64_t total = d.n_inst << d.mbits;
-  const uint32_t mmask = (1u << d.mbits) - 1u;
-  const int64_t sigma0 = sig[0];
-  for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < total; g += (int64_t)gridDim.x * 256) {
-    const int64_t inst = g >> d.mbits;
-    const uint32_t m = (uint32_t)g & mmask;
-    const int64_t s = d.dep ? inst / d.w : 0;
-    const int64_t j = d.dep ? inst - s * d.w : inst;
-    const int64_t sigma = sigma0 + s;
-    const int64_t ai = operand_instance(d.A, glA, j, s, sigma);
-    const int64_t bi = operand_instance(d.B, glB, j, s, sigma);
-    const float2* __restrict__ pa = reinterpret_cast<const float2*>(ws + d.A.off + ai * d.A.inst_bytes);
-    const float2* __restrict__ pb = reinterpret_cast<const float2*>(ws + d.B.off + bi * d.B.inst_bytes);
-    float2* __restrict__ pc = reinterpret_cast<float2*>(ws + d.c_off + inst * d.c_inst_bytes);
-    const uint32_t oa = tab[TAB_AM * kTabSize + m];
-    const uint32_t oc = tab[TAB_CM * kTabSize + m];
-    float2 a[KB];
-#pragma unroll
-    for (int k = 0; k < KB; ++k) a[k] = pa[oa + tab[TAB_AK * kTabSize + k]];
-#pragma unroll
-    for (int n = 0; n < NB; ++n) {
-      float2 c = make_float2(0.f, 0.f);
-      const uint32_t bn = tab[TAB_BN * kTabSize + n];
-#pragma unroll
-      for (int k = 0; k < KB; ++k) cmac(c, a[k], pb[bn + tab[TAB_BK * kTabSize + k]]);
-      pc[oc + tab[TAB_CN * kTabSize + n]] = c;
-    }
-  }
-}
-
-// Any shape: one lane per (instance, m, n), loops over k.  Used when the
-// small operand is too large for the templated kernels.
-__global__ __launch_bounds__(256) void k_stream_generic(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
-  const uint32_t* __restrict__ tab = reinterpret_cast<const uint32_t*>(ws + d.tab_off);
-  const int32_t* __restrict__ glA = reinterpret_cast<const int32_t*>(ws + d.A.gmap_off);
-  const int32_t* __restrict__ glB = reinterpret_cast<const int32_t*>(ws + d.B.gmap_off);
-  const int cb = d.mbits + d.nbits;
-  const int64_t total = d.n_inst << cb;
-  const int64_t sigma0 = sig[0];
-  const uint64_t kcount = (uint64_t)1 << d.kbits;
-  for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < total; g += (int64_t)gridDim.x * 256) {
-    const int64_t inst = g >> cb;
-    const uint64_t mn = (uint64_t)g & (((uint64_t)1 << cb) - 1);
-    const uint32_t m = (uint32_t)(mn & (((uint64_t)1 << d.mbits) - 1));
-    const uint32_t n = (uint32_t)(mn >> d.mbits);
-    const int64_t s = d.dep ? inst / d.w : 0;
-    const int64_t j = d.dep ? inst - s * d.w : inst;
-    const int64_t sigma = sigma0 + s;
-    const int64_t ai = operand_instance(d.A, glA, j, s, sigma);
-    const int64_t bi = operand_instance(d.B, glB, j, s, sigma);
-    const float2* __restrict__ pa = reinterpret_cast<const float2*>(ws + d.A.off + ai * d.A.inst_bytes);
-    const float2* __restrict__ pb = reinterpret_cast<const float2*>(ws + d.B.off + bi * d.B.inst_bytes);
-    float2* __restrict__ pc = reinterpret_cast<float2*>(ws + d.c_off + inst * d.c_inst_bytes);
-    const uint32_t oa = tlook(tab + TAB_AM * kTabSize, m);
-    const uint32_t ob = tlook(tab + TAB_BN * kTabSize, n);
-    float2 c = make_float2(0.f, 0.f);
-    for (uint64_t k = 0; k < kcount; ++k) {
-      const uint32_t kk = (uint32_t)k;
-      cmac(c, pa[oa + tlook(tab + TAB_AK * kTabSize, kk)], pb[ob + tlook(tab + TAB_BK * kTabSize, kk)]);
-    }
-    pc[tlook(tab + TAB_CM * kTabSize, m) + tlook(tab + TAB_CN * kTabSize, n)] = c;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // MFMA complex GEMM
@@ -329,46 +213,6 @@ __global__ void k_set_i64(int64_t* p, int64_t v) {
 
 // ---------------------------------------------------------------------------
 // launchers
-
-template <int KB, int NB>
-static hipError_t launch_stream_t(const NodeDesc& d, uint64_t ws, const int64_t* sig, hipStream_t st) {
-  if (d.mbits >= 8) {
-    const int64_t blocks = d.n_inst << (d.mbits - 8);
-    hipLaunchKernelGGL((k_stream_wide<KB, NB>), dim3(grid_for(blocks)), dim3(256), 0, st, d, ws, sig);
-  } else {
-    const int64_t blocks = ((d.n_inst << d.mbits) + 255) / 256;
-    hipLaunchKernelGGL((k_stream_narrow<KB, NB>), dim3(grid_for(blocks)), dim3(256), 0, st, d, ws, sig);
-  }
-  return hipGetLastError();
-}
-
-template <int KB>
-static hipError_t launch_stream_n(const NodeDesc& d, uint64_t ws, const int64_t* sig, hipStream_t st) {
-  switch (d.nbits) {
-    case 0: return launch_stream_t<KB, 1>(d, ws, sig, st);
-    case 1: return launch_stream_t<KB, 2>(d, ws, sig, st);
-    case 2: return launch_stream_t<KB, 4>(d, ws, sig, st);
-    case 3: return launch_stream_t<KB, 8>(d, ws, sig, st);
-    case 4: return launch_stream_t<KB, 16>(d, ws, sig, st);
-  }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_stream(const NodeDesc& d, uint64_t ws, const int64_t* sig, hipStream_t st) {
-  if (d.n_inst == 0) return hipSuccess;
-  if (d.kbits <= 4 && d.nbits <= 4) {
-    switch (d.kbits) {
-      case 0: return launch_stream_n<1>(d, ws, sig, st);
-      case 1: return launch_stream_n<2>(d, ws, sig, st);
-      case 2: return launch_stream_n<4>(d, ws, sig, st);
-      case 3: return launch_stream_n<8>(d, ws, sig, st);
-      case 4: return launch_stream_n<16>(d, ws, sig, st);
-    }
-  }
-  const int64_t blocks = ((d.n_inst << (d.mbits + d.nbits)) + 255) / 256;
-  hipLaunchKernelGGL(k_stream_generic, dim3(grid_for(blocks)), dim3(256), 0, st, d, ws, sig);
-  return hipGetLastError();
-}
 
 struct MfmaCfg {
   int tm_bits, tn_bits, tk_bits;

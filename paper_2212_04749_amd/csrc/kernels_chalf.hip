@@ -9,7 +9,6 @@ namespace matnc {
 
 bool chalf_available() { return false; }
 
-hipError_t launch_stream_h(const NodeDesc&, uint64_t, const int64_t*, hipStream_t) { return hipErrorNotSupported; }
 int mfma_h_config_count() { return 0; }
 bool mfma_h_config_fits(int, int, int, int) { return false; }
 hipError_t launch_mfma_h(const NodeDesc&, int, uint64_t, const int64_t*, hipStream_t) { return hipErrorNotSupported; }

@@ -54,8 +54,14 @@ def run(torch, pos, A, Bm, nm, nn, nk, kernel):
 
 
 STREAM_CASES = [
-    (8, 2, 2, 1), (10, 0, 2, 2), (9, 2, 0, 1), (12, 4, 4, 1), (5, 3, 2, 7), (3, 1, 1, 33),
-    (0, 2, 3, 5), (7, 4, 1, 3), (14, 2, 3, 1), (2, 3, 6, 4), (1, 5, 5, 2),
+    # small K and N: one lane per m, 1 / 2 / 4 m-chunks per lane
+    (8, 2, 2, 1), (10, 0, 2, 2), (9, 2, 0, 1), (12, 4, 4, 1), (9, 4, 4, 3), (11, 3, 3, 2),
+    # instances below 256 elements
+    (5, 3, 2, 7), (3, 1, 1, 33), (0, 2, 3, 5), (7, 4, 1, 3), (14, 2, 3, 1),
+    # large K: K split over lane groups
+    (2, 3, 6, 4), (8, 2, 11, 3), (0, 0, 10, 4), (10, 1, 7, 2), (4, 3, 9, 5), (9, 0, 6, 2),
+    # generic
+    (1, 5, 5, 2), (3, 6, 2, 2),
 ]
 
 
