@@ -36,6 +36,8 @@ struct OpDesc {
   int32_t dep;          // 1: operand instances repeat per slice
   int32_t nsv;          // leaf: 2^nsb slice variants per key; else 1
   int32_t nsb;          // number of sliced indices on the leaf
+  int32_t half;         // complex-half plans: 1 = stored as FP16 with scales, 0 = FP32
+  int32_t pad0;
   int8_t sbit[kMaxLeafSliced];  // sigma bit of each sliced index
 };
 
@@ -49,12 +51,12 @@ struct NodeDesc {
   int32_t w;             // reuse-tree width w(v)
   int32_t dep;           // output instances repeat per slice
   int32_t mbits, nbits, kbits;
-  int32_t pad;
+  int32_t c_half;        // complex-half plans: output stored as FP16 (1) or FP32 (0)
 };
 
-// Complex-half scaling of one stored instance: true value = stored half *
-// 2^e; mx = largest |re| or |im| of the stored halves (float bits, so that
-// unsigned atomicMax orders it).
+// Scaling of one stored instance in complex-half plans: true value = stored
+// value * 2^e (e = 0 for FP32 storage); mx = largest |re| or |im| of the
+// stored values (float bits, so that unsigned atomicMax orders it).
 struct HalfScale {
   int32_t e;
   uint32_t mx;

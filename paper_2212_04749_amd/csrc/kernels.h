@@ -12,6 +12,8 @@ hipError_t launch_stream(const NodeDesc& d, uint64_t ws, const int64_t* sig, hip
 int mfma_config_count();
 bool mfma_config_fits(int cfg, int mbits, int nbits, int kbits);
 hipError_t launch_mfma(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st);
+// same kernel, also recording each output instance's maximum (complex-half plans)
+hipError_t launch_mfma_rec(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st);
 hipError_t launch_slice_sum(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t k, int open_bits,
                             double* amps, hipStream_t st);
 
@@ -23,6 +25,8 @@ bool mfma_h_config_fits(int cfg, int mbits, int nbits, int kbits);
 hipError_t launch_mfma_h(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st);
 hipError_t launch_slice_sum_h(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t k,
                               int open_bits, double* amps, hipStream_t st);
+
+hipError_t launch_zero(uint64_t ptr, uint64_t bytes, hipStream_t st);
 
 // shared
 hipError_t launch_xeb(const double* amps, int64_t count, int n_qubits, double* out, hipStream_t st);

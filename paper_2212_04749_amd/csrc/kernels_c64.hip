@@ -27,7 +27,9 @@ namespace matnc {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 // Tile: TM = 32*RM*WM values of m, TN = 16*RN*WN complex n, TK complex k.
-template <int RM, int RN, int WM, int WN, int TK>
+// REC: also record the output instance's largest |component| (complex-half
+// plans, whose FP32 stem tensors feed FP16 consumers).
+template <int RM, int RN, int WM, int WN, int TK, bool REC>
 __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
   constexpr int NT = 64 * WM * WN;
   constexpr int TM = 32 * RM * WM;
@@ -150,6 +152,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
     }
 
     // epilogue: lane holds C[m][n] (re, im) in registers (r, r+1), r even
+    float mx = 0.f;
 #pragma unroll
     for (int i = 0; i < RM; ++i) {
       const uint32_t m = m0 + (wm * RM + i) * 32 + l32;
@@ -161,7 +164,17 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
           const int row = 8 * (r >> 2) + 4 * half + (r & 3);
           const uint32_t n = n0 + (wn * RN + q) * 16 + (row >> 1);
           pc[om + tlook(tab + TAB_CN * kTabSize, n)] = make_float2(acc[i][q][r], acc[i][q][r + 1]);
+          if (REC) mx = fmaxf(mx, fmaxf(fabsf(acc[i][q][r]), fabsf(acc[i][q][r + 1])));
         }
+      }
+    }
+    if (REC) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+      if (lane == 0) {
+        HalfScale* sc = reinterpret_cast<HalfScale*>(ws + d.c_scale_off) + inst;
+        sc->e = 0;
+        if (mx > 0.f) atomicMax(&sc->mx, __float_as_uint(mx));
       }
     }
   }
@@ -233,20 +246,29 @@ bool mfma_config_fits(int cfg, int mbits, int nbits, int kbits) {
   return mbits >= c.tm_bits && nbits >= c.tn_bits && kbits >= c.tk_bits;
 }
 
-hipError_t launch_mfma(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
+template <bool REC>
+static hipError_t launch_mfma_t(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
   if (d.n_inst == 0) return hipSuccess;
   if (!mfma_config_fits(cfg, d.mbits, d.nbits, d.kbits)) return hipErrorInvalidValue;
   const MfmaCfg& c = kMfmaCfgs[cfg];
   const int64_t tiles = ((int64_t)1 << (d.mbits - c.tm_bits)) * ((int64_t)1 << (d.nbits - c.tn_bits));
   const unsigned grid = grid_for(d.n_inst * tiles);
   switch (cfg) {
-    case 0: hipLaunchKernelGGL((k_mfma<2, 1, 2, 2, 8>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 1: hipLaunchKernelGGL((k_mfma<2, 2, 2, 2, 8>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 2: hipLaunchKernelGGL((k_mfma<1, 1, 2, 2, 8>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 3: hipLaunchKernelGGL((k_mfma<4, 1, 2, 2, 8>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 0: hipLaunchKernelGGL((k_mfma<2, 1, 2, 2, 8, REC>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 1: hipLaunchKernelGGL((k_mfma<2, 2, 2, 2, 8, REC>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 2: hipLaunchKernelGGL((k_mfma<1, 1, 2, 2, 8, REC>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 3: hipLaunchKernelGGL((k_mfma<4, 1, 2, 2, 8, REC>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_mfma(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
+  return launch_mfma_t<false>(d, cfg, ws, sig, st);
+}
+
+hipError_t launch_mfma_rec(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
+  return launch_mfma_t<true>(d, cfg, ws, sig, st);
 }
 
 hipError_t launch_slice_sum(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t k, int open_bits,

@@ -1,19 +1,306 @@
-// complex-half kernels (FP16 storage, per-instance power-of-two exponent,
-// FP16 MFMA with FP32 accumulation).
+// complex-half kernels: FP16 (re, im) storage with a per-instance power-of-two
+// exponent, FP16 MFMA with FP32 accumulation.
+//
+//  * k_mfma_h: C[m, n] = sum_k A[m, k] B[k, n] with an FP16 output, on
+//    v_mfma_f32_32x32x8f16
+//    through the real embedding [Ar Ai] x [[Br, Bi], [-Bi, Br]]: each
+//    instruction covers four complex k.  For its column m a lane supplies
+//    (Ar, Ai) of two consecutive k -- exactly two stored half2 values -- and
+//    for its row 2n + d it supplies (Br, -Bi) (d = 0) or (Bi, Br) (d = 1) of
+//    the same two k.  The products of FP16 inputs are exact in the FP32
+//    accumulator; the output is multiplied by 2^(15 - ex), ex = ceil of
+//    log2 of the bound 2^(kbits+1) mx_A mx_B, stored as FP16 below 2^15, and
+//    its measured maximum recorded for the next step.  An operand stored in
+//    FP32 (leaves and stem tensors of the plan) is scaled by a power of two
+//    and rounded to FP16 as it is loaded.
+//  * k_slice_sum_h: FP64 sum of half * 2^e over slices, in slice order.
+//  * k_zero: clears the scale slots of a launch sequence (a kernel rather
+//    than a memset so that it can live inside a captured graph).
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
+#include <stdint.h>
 
 #include "desc.h"
+#include "device_common.h"
 #include "kernels.h"
 
 namespace matnc {
 
-bool chalf_available() { return false; }
+bool chalf_available() { return true; }
 
-int mfma_h_config_count() { return 0; }
-bool mfma_h_config_fits(int, int, int, int) { return false; }
-hipError_t launch_mfma_h(const NodeDesc&, int, uint64_t, const int64_t*, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_slice_sum_h(const OpDesc&, uint64_t, const int64_t*, int, int64_t, int, double*, hipStream_t) {
-  return hipErrorNotSupported;
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t h2bits(__half2 h) { return *reinterpret_cast<uint32_t*>(&h); }
+
+// element i of an operand as half2 bits: FP16 storage as is, FP32 storage
+// scaled by c and rounded to nearest
+__device__ __forceinline__ uint32_t ld_h2bits(uint64_t base, uint32_t i, int half, float c) {
+  if (half) return reinterpret_cast<const uint32_t*>(base)[i];
+  const float2 v = reinterpret_cast<const float2*>(base)[i];
+  return h2bits(__float22half2_rn(make_float2(v.x * c, v.y * c)));
+}
+
+// TM = 32*RM*WM values of m, TN = 16*RN*WN complex n, TK complex k (multiple of 4)
+template <int RM, int RN, int WM, int WN, int TK>
+__global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int TM = 32 * RM * WM;
+  constexpr int TN = 16 * RN * WN;
+  constexpr int EA = TK * TM / NT;
+  constexpr int EB = TK * TN / NT;
+  static_assert(EA * NT == TK * TM && EB * NT == TK * TN, "tile must split evenly over threads");
+  static_assert(TK % 4 == 0, "four complex k per instruction");
+  __shared__ uint32_t As[2][TK * TM];  // half2 bits, [k][m]
+  __shared__ uint32_t Bs[2][TK * TN];  // half2 bits, [k][n]
+
+  const uint32_t* __restrict__ tab = reinterpret_cast<const uint32_t*>(ws + d.tab_off);
+  const int32_t* __restrict__ glA = reinterpret_cast<const int32_t*>(ws + d.A.gmap_off);
+  const int32_t* __restrict__ glB = reinterpret_cast<const int32_t*>(ws + d.B.gmap_off);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave % WM;
+  const int wn = wave / WM;
+  const int64_t mt_count = (int64_t)1 << (d.mbits - __builtin_ctz(TM));
+  const int64_t nt_count = (int64_t)1 << (d.nbits - __builtin_ctz(TN));
+  const int64_t tiles = mt_count * nt_count;
+  const int ksteps = 1 << (d.kbits - __builtin_ctz(TK));
+  const int64_t sigma0 = sig[0];
+  const int half = lane >> 5;
+  const int l32 = lane & 31;
+  const int dsel = l32 & 1;
+  const int ncol = l32 >> 1;
+
+  for (int64_t blk = blockIdx.x; blk < d.n_inst * tiles; blk += gridDim.x) {
+    const int64_t inst = blk / tiles;
+    const int64_t t = blk - inst * tiles;
+    const uint32_t m0 = (uint32_t)((t % mt_count) * TM);
+    const uint32_t n0 = (uint32_t)((t / mt_count) * TN);
+    const int64_t s = d.dep ? inst / d.w : 0;
+    const int64_t j = d.dep ? inst - s * d.w : inst;
+    const int64_t sigma = sigma0 + s;
+    const int64_t ai = operand_instance(d.A, glA, j, s, sigma);
+    const int64_t bi = operand_instance(d.B, glB, j, s, sigma);
+    const uint64_t pa = ws + d.A.off + ai * d.A.inst_bytes;
+    const uint64_t pb = ws + d.B.off + bi * d.B.inst_bytes;
+    __half2* __restrict__ pc = reinterpret_cast<__half2*>(ws + d.c_off + inst * d.c_inst_bytes);
+    // operand scales; an FP32 operand is converted on load with a power of two
+    // that puts its largest component in [2^13, 2^14)
+    const HalfScale sa = reinterpret_cast<const HalfScale*>(ws + d.A.scale_off)[ai];
+    const HalfScale sb = reinterpret_cast<const HalfScale*>(ws + d.B.scale_off)[bi];
+    int ea = sa.e, eb = sb.e;
+    float mxa = __uint_as_float(sa.mx), mxb = __uint_as_float(sb.mx);
+    float ca = 1.f, cb = 1.f;
+    if (!d.A.half && mxa > 0.f) {
+      int ex;
+      frexpf(mxa, &ex);
+      ea = ex - 14;
+      ca = ldexpf(1.f, -ea);
+      mxa *= ca;
+    }
+    if (!d.B.half && mxb > 0.f) {
+      int ex;
+      frexpf(mxb, &ex);
+      eb = ex - 14;
+      cb = ldexpf(1.f, -eb);
+      mxb *= cb;
+    }
+    const int ha = d.A.half, hb = d.B.half;
+
+    uint32_t aoff[EA], boff[EB];
+    int akk[EA], bkk[EB], amm[EA], bnn[EB];
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int flat = e * NT + tid;
+      amm[e] = flat % TM;
+      akk[e] = flat / TM;
+      aoff[e] = tlook(tab + TAB_AM * kTabSize, m0 + amm[e]) + tab[TAB_AK * kTabSize + akk[e]];
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int flat = e * NT + tid;
+      bnn[e] = flat % TN;
+      bkk[e] = flat / TN;
+      boff[e] = tlook(tab + TAB_BN * kTabSize, n0 + bnn[e]) + tab[TAB_BK * kTabSize + bkk[e]];
+    }
+    uint32_t ra[EA], rb[EB];
+    auto gload = [&](int ks) {
+      const uint32_t k0 = (uint32_t)ks * TK;
+      const uint32_t kba = tlook(tab + TAB_AK * kTabSize, k0);
+      const uint32_t kbb = tlook(tab + TAB_BK * kTabSize, k0);
+#pragma unroll
+      for (int e = 0; e < EA; ++e) ra[e] = ld_h2bits(pa, aoff[e] + kba, ha, ca);
+#pragma unroll
+      for (int e = 0; e < EB; ++e) rb[e] = ld_h2bits(pb, boff[e] + kbb, hb, cb);
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int e = 0; e < EA; ++e) As[buf][akk[e] * TM + amm[e]] = ra[e];
+#pragma unroll
+      for (int e = 0; e < EB; ++e) Bs[buf][bkk[e] * TN + bnn[e]] = rb[e];
+    };
+
+    floatx16 acc[RM][RN];
+#pragma unroll
+    for (int i = 0; i < RM; ++i)
+#pragma unroll
+      for (int q = 0; q < RN; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][q][r] = 0.f;
+
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int ks = 0; ks < ksteps; ++ks) {
+      const int buf = ks & 1;
+      if (ks + 1 < ksteps) gload(ks + 1);
+#pragma unroll
+      for (int kq = 0; kq < TK; kq += 4) {
+        const int k0 = kq + 2 * half;  // this lane's two complex k
+        halfx4 yv[RM], xv[RN];
+#pragma unroll
+        for (int i = 0; i < RM; ++i) {
+          const int m = (wm * RM + i) * 32 + l32;
+          const uint32_t u0 = As[buf][k0 * TM + m], u1 = As[buf][(k0 + 1) * TM + m];
+          const __half2 h0 = *reinterpret_cast<const __half2*>(&u0);
+          const __half2 h1 = *reinterpret_cast<const __half2*>(&u1);
+          yv[i] = halfx4{(_Float16)__low2half(h0), (_Float16)__high2half(h0), (_Float16)__low2half(h1),
+                         (_Float16)__high2half(h1)};
+        }
+#pragma unroll
+        for (int q = 0; q < RN; ++q) {
+          const int n = (wn * RN + q) * 16 + ncol;
+          const uint32_t u0 = Bs[buf][k0 * TN + n], u1 = Bs[buf][(k0 + 1) * TN + n];
+          const __half2 h0 = *reinterpret_cast<const __half2*>(&u0);
+          const __half2 h1 = *reinterpret_cast<const __half2*>(&u1);
+          const _Float16 r0 = (_Float16)__low2half(h0), i0 = (_Float16)__high2half(h0);
+          const _Float16 r1 = (_Float16)__low2half(h1), i1 = (_Float16)__high2half(h1);
+          xv[q] = dsel ? halfx4{i0, r0, i1, r1} : halfx4{r0, -i0, r1, -i1};
+        }
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+#pragma unroll
+          for (int q = 0; q < RN; ++q)
+            acc[i][q] = __builtin_amdgcn_mfma_f32_32x32x8f16(xv[q], yv[i], acc[i][q], 0, 0, 0);
+      }
+      if (ks + 1 < ksteps) lstore(buf ^ 1);
+      __syncthreads();
+    }
+
+    // output scale of this instance
+    const float bound = ldexpf(mxa * mxb, d.kbits + 1);
+    int ex = 0;
+    if (bound > 0.f) frexpf(bound, &ex);
+    const float f = ldexpf(1.f, 15 - ex);
+    float mx = 0.f;
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+      const uint32_t m = m0 + (wm * RM + i) * 32 + l32;
+      const uint32_t om = tlook(tab + TAB_CM * kTabSize, m);
+#pragma unroll
+      for (int q = 0; q < RN; ++q) {
+#pragma unroll
+        for (int r = 0; r < 16; r += 2) {
+          const int row = 8 * (r >> 2) + 4 * half + (r & 3);
+          const uint32_t n = n0 + (wn * RN + q) * 16 + (row >> 1);
+          const __half2 h = __float22half2_rn(make_float2(acc[i][q][r] * f, acc[i][q][r + 1] * f));
+          pc[om + tlook(tab + TAB_CN * kTabSize, n)] = h;
+          const float2 back = __half22float2(h);
+          mx = fmaxf(mx, fmaxf(fabsf(back.x), fabsf(back.y)));
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if (lane == 0) {
+      HalfScale* sc = reinterpret_cast<HalfScale*>(ws + d.c_scale_off) + inst;
+      sc->e = ea + eb + ex - 15;
+      if (mx > 0.f) atomicMax(&sc->mx, __float_as_uint(mx));
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_slice_sum_h(OpDesc root, uint64_t ws, const int64_t* __restrict__ sig,
+                                                     int nb, int64_t k, int open_bits, double2* __restrict__ amps) {
+  const int32_t* __restrict__ gmap = reinterpret_cast<const int32_t*>(ws + root.gmap_off);
+  const HalfScale* __restrict__ sc = reinterpret_cast<const HalfScale*>(ws + root.scale_off);
+  const int64_t total = k << open_bits;
+  const int64_t sigma0 = sig[0];
+  const int64_t omask = ((int64_t)1 << open_bits) - 1;
+  for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < total; g += (int64_t)gridDim.x * 256) {
+    const int64_t i = g >> open_bits;
+    const int64_t o = g & omask;
+    double2 acc = amps[g];
+    for (int s = 0; s < nb; ++s) {
+      const int64_t inst = operand_instance(root, gmap, i, s, sigma0 + s);
+      const uint64_t base = ws + root.off + inst * root.inst_bytes;
+      const float2 v = root.half ? __half22float2(reinterpret_cast<const __half2*>(base)[o])
+                                 : reinterpret_cast<const float2*>(base)[o];
+      const int e = sc[inst].e;
+      acc.x += ldexp((double)v.x, e);
+      acc.y += ldexp((double)v.y, e);
+    }
+    amps[g] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_zero(uint4* __restrict__ p, int64_t n16) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (int64_t)gridDim.x * 256)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// ---------------------------------------------------------------------------
+
+struct MfmaCfgH {
+  int tm_bits, tn_bits, tk_bits;
+};
+
+static const MfmaCfgH kMfmaCfgsH[] = {
+    {7, 6, 4},  // 0: RM=2 RN=2 WM=2 WN=2, TK=16 -> TM=128, TN=64
+    {7, 5, 4},  // 1: RM=2 RN=1 WM=2 WN=2, TK=16 -> TM=128, TN=32
+    {6, 5, 4},  // 2: RM=1 RN=1 WM=2 WN=2, TK=16 -> TM=64,  TN=32
+    {8, 5, 4},  // 3: RM=4 RN=1 WM=2 WN=2, TK=16 -> TM=256, TN=32
+};
+
+int mfma_h_config_count() { return (int)(sizeof(kMfmaCfgsH) / sizeof(kMfmaCfgsH[0])); }
+
+bool mfma_h_config_fits(int cfg, int mbits, int nbits, int kbits) {
+  if (cfg < 0 || cfg >= mfma_h_config_count()) return false;
+  const MfmaCfgH& c = kMfmaCfgsH[cfg];
+  return mbits >= c.tm_bits && nbits >= c.tn_bits && kbits >= c.tk_bits;
+}
+
+hipError_t launch_mfma_h(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
+  if (d.n_inst == 0) return hipSuccess;
+  if (!mfma_h_config_fits(cfg, d.mbits, d.nbits, d.kbits)) return hipErrorInvalidValue;
+  const MfmaCfgH& c = kMfmaCfgsH[cfg];
+  const int64_t tiles = ((int64_t)1 << (d.mbits - c.tm_bits)) * ((int64_t)1 << (d.nbits - c.tn_bits));
+  const unsigned grid = grid_for(d.n_inst * tiles);
+  switch (cfg) {
+    case 0: hipLaunchKernelGGL((k_mfma_h<2, 2, 2, 2, 16>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 1: hipLaunchKernelGGL((k_mfma_h<2, 1, 2, 2, 16>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 2: hipLaunchKernelGGL((k_mfma_h<1, 1, 2, 2, 16>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 3: hipLaunchKernelGGL((k_mfma_h<4, 1, 2, 2, 16>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_slice_sum_h(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t k, int open_bits,
+                              double* amps, hipStream_t st) {
+  const int64_t total = k << open_bits;
+  if (total == 0 || nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slice_sum_h, dim3(grid_for((total + 255) / 256)), dim3(256), 0, st, root, ws, sig, nb, k,
+                     open_bits, reinterpret_cast<double2*>(amps));
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(uint64_t ptr, uint64_t bytes, hipStream_t st) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3(grid_for((n16 + 255) / 256)), dim3(256), 0, st, reinterpret_cast<uint4*>(ptr), n16);
+  return hipGetLastError();
 }
 
 }  // namespace matnc

@@ -3,24 +3,26 @@
 // compute (a big tensor times a gate-sized one, or a batched matrix-vector
 // product), so the kernels are built for HBM bandwidth:
 //
-//  * k_wide<P, KB, NB, R>  small K (<= 16) and N (<= 16): every lane owns R
+//  * k_wide<FL, KB, R>     small K (<= 16) and N (<= 16): every lane owns R
 //    values of m spaced 256 apart (R x KB loads in flight), B is staged once
 //    per block in LDS, all offset tables that do not depend on m are hoisted.
 //    A block covers 256*R consecutive m of one instance, so instance
 //    decoding and B are block-uniform.
-//  * k_narrow<P, KB, NB>   the same for instances smaller than 256 elements:
+//  * k_narrow<FL, KB>      the same for instances smaller than 256 elements:
 //    one lane per (instance, m).
-//  * k_kred<P, NB>         large K: lanes own m (coalesced reads of A along
+//  * k_kred<FL, NB>        large K: lanes own m (coalesced reads of A along
 //    its low bits), groups of lanes split K, partial sums meet in LDS.
-//  * k_generic<P>          anything else (one lane per output element).
+//  * k_generic<FL>         anything else (one lane per output element).
 //
-// Precision policy P: C64 stores float2; CH stores __half2 with a
-// per-instance exponent e (value = half * 2^e) and the instance maximum mx.
-// The output exponent is chosen from the operands' measured maxima so that
-// |Re|, |Im| of every output (bounded by 2^(kbits+1) mx_A mx_B 2^(e_A+e_B))
-// is stored below 2^15 (no FP16 overflow); the maximum of the stored
-// output is measured (block reduction + unsigned atomicMax on the float
-// bits, exact because all values are non-negative) for the next step.
+// Precision policy P: C64 plans store float2 everywhere.  MIX (complex-half
+// plans) stores each tensor as __half2 with a per-instance exponent e
+// (value = half * 2^e) or as float2 (e = 0), as the plan decided; every
+// stored instance also carries its measured maximum mx.  A FP16 output's
+// exponent is chosen from the operands' maxima so that |Re|, |Im| of every
+// output (bounded by 2^(kbits+1) mx_A mx_B 2^(e_A+e_B)) is stored below
+// 2^15 (no FP16 overflow); the maximum of the stored output is measured
+// (block reduction + unsigned atomicMax on the float bits, exact because
+// all values are non-negative) for the next step.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -31,56 +33,65 @@
 
 namespace matnc {
 
-struct C64 {
-  using T = float2;
-  static constexpr bool kHalf = false;
-  __device__ static __forceinline__ float2 ld(const T* p, uint32_t i) { return p[i]; }
-};
+// Storage flags FL (compile-time): bit 3 = complex-half plan (scales
+// tracked); bit 0 / 1 / 2 = A / B / C stored as FP16 (else FP32).
+constexpr int kMixBit = 8;
 
-struct CH {
-  using T = __half2;
-  static constexpr bool kHalf = true;
-  __device__ static __forceinline__ float2 ld(const T* p, uint32_t i) { return __half22float2(p[i]); }
-};
+template <int FL, int WHICH>
+__device__ __forceinline__ float2 ldop(uint64_t base, uint32_t i) {
+  if constexpr ((FL & kMixBit) && (FL & WHICH)) return __half22float2(reinterpret_cast<const __half2*>(base)[i]);
+  return reinterpret_cast<const float2*>(base)[i];
+}
 
-// Output scale of one instance (complex-half); identity for complex64.
+// Output scale of one instance; identity for complex64 plans.
 struct OutScale {
   float f;       // multiply the FP32 result by f before storing
   int32_t e;     // exponent recorded for the output instance
 };
 
-template <class P>
+template <int FL>
 __device__ __forceinline__ OutScale out_scale(const NodeDesc& d, uint64_t ws, int64_t ai, int64_t bi) {
   OutScale o{1.f, 0};
-  if constexpr (P::kHalf) {
+  if constexpr ((FL & kMixBit) != 0) {
     const HalfScale sa = reinterpret_cast<const HalfScale*>(ws + d.A.scale_off)[ai];
     const HalfScale sb = reinterpret_cast<const HalfScale*>(ws + d.B.scale_off)[bi];
-    const float bound = ldexpf(__uint_as_float(sa.mx) * __uint_as_float(sb.mx), d.kbits + 1);
-    int ex = 0;
-    if (bound > 0.f) frexpf(bound, &ex);  // bound < 2^ex
-    o.e = sa.e + sb.e + ex - 15;
-    o.f = ldexpf(1.f, 15 - ex);
+    if constexpr ((FL & 4) != 0) {
+      const float bound = ldexpf(__uint_as_float(sa.mx) * __uint_as_float(sb.mx), d.kbits + 1);
+      int ex = 0;
+      if (bound > 0.f) frexpf(bound, &ex);  // bound < 2^ex
+      o.e = sa.e + sb.e + ex - 15;
+      o.f = ldexpf(1.f, 15 - ex);
+    } else {
+      o.e = 0;
+      o.f = ldexpf(1.f, sa.e + sb.e);
+    }
   }
   return o;
 }
 
-template <class P>
-__device__ __forceinline__ float put(typename P::T* p, uint32_t i, float2 c, const OutScale& s) {
-  if constexpr (P::kHalf) {
-    const __half2 h = __float22half2_rn(make_float2(c.x * s.f, c.y * s.f));
-    p[i] = h;
-    const float2 back = __half22float2(h);
-    return fmaxf(fabsf(back.x), fabsf(back.y));
+// store one output element; returns the largest stored |component|
+template <int FL>
+__device__ __forceinline__ float put(uint64_t base, uint32_t i, float2 c, const OutScale& s) {
+  if constexpr ((FL & kMixBit) != 0) {
+    const float2 v = make_float2(c.x * s.f, c.y * s.f);
+    if constexpr ((FL & 4) != 0) {
+      const __half2 h = __float22half2_rn(v);
+      reinterpret_cast<__half2*>(base)[i] = h;
+      const float2 back = __half22float2(h);
+      return fmaxf(fabsf(back.x), fabsf(back.y));
+    }
+    reinterpret_cast<float2*>(base)[i] = v;
+    return fmaxf(fabsf(v.x), fabsf(v.y));
   } else {
-    p[i] = c;
+    reinterpret_cast<float2*>(base)[i] = c;
     return 0.f;
   }
 }
 
-template <class P>
+template <int FL>
 __device__ __forceinline__ void record_scale(const NodeDesc& d, uint64_t ws, int64_t inst, const OutScale& s,
                                              float mx, bool writer) {
-  if constexpr (P::kHalf) {
+  if constexpr ((FL & kMixBit) != 0) {
     HalfScale* sc = reinterpret_cast<HalfScale*>(ws + d.c_scale_off) + inst;
     if (writer) sc->e = s.e;
     if (mx > 0.f) atomicMax(&sc->mx, __float_as_uint(mx));
@@ -100,20 +111,13 @@ __device__ __forceinline__ float segment_max(float v, int seg) {
   return v;
 }
 
-template <class P>
+// record the output maximum: one atomic per wave, no block barrier
+template <int FL>
 __device__ __forceinline__ void block_record(const NodeDesc& d, uint64_t ws, int64_t inst, const OutScale& s, float mx,
-                                             float* red) {
-  if constexpr (P::kHalf) {
+                                             float* /*red*/) {
+  if constexpr ((FL & kMixBit) != 0) {
     mx = wave_max(mx);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) red[wave] = mx;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      float m = 0.f;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, red[w]);
-      record_scale<P>(d, ws, inst, s, m, true);
-    }
-    __syncthreads();
+    if ((threadIdx.x & 63) == 0) record_scale<FL>(d, ws, inst, s, mx, true);
   }
 }
 
@@ -139,22 +143,21 @@ __device__ __forceinline__ InstPtrs instance_ptrs(const NodeDesc& d, uint64_t ws
 
 // ---------------------------------------------------------------------------
 
-template <class P, int KB, int NB, int R>
+// N (<= 16) is a runtime bound: outputs are produced one n at a time
+template <int FL, int KB, int R>
 __global__ __launch_bounds__(256) void k_wide(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
-  using T = typename P::T;
   constexpr int LR = (R == 1) ? 0 : (R == 2) ? 1 : (R == 4) ? 2 : 3;
-  __shared__ float2 Bs[KB * NB];
+  __shared__ float2 Bs[KB * 16];
   __shared__ float red[4];
   const uint32_t* __restrict__ tab = reinterpret_cast<const uint32_t*>(ws + d.tab_off);
   const uint32_t* TA = tab + TAB_AM * kTabSize;
   const uint32_t* TC = tab + TAB_CM * kTabSize;
   const int tid = threadIdx.x;
+  const int NB = 1 << d.nbits;
   const uint32_t oa_lo = TA[tid], oc_lo = TC[tid];
-  uint32_t tak[KB], tcn[NB];
+  uint32_t tak[KB];
 #pragma unroll
   for (int k = 0; k < KB; ++k) tak[k] = tab[TAB_AK * kTabSize + k];
-#pragma unroll
-  for (int n = 0; n < NB; ++n) tcn[n] = tab[TAB_CN * kTabSize + n];
   // this lane's B element when staging (KB * NB <= 256)
   uint32_t ob_mine = 0;
   if (tid < KB * NB) ob_mine = tab[TAB_BK * kTabSize + tid / NB] + tab[TAB_BN * kTabSize + tid % NB];
@@ -165,10 +168,7 @@ __global__ __launch_bounds__(256) void k_wide(NodeDesc d, uint64_t ws, const int
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
     const InstPtrs ip = instance_ptrs(d, ws, blk >> sh, sigma0);
     const uint32_t hi0 = (uint32_t)(blk & (bpi - 1)) << LR;
-    const T* pa = reinterpret_cast<const T*>(ip.pa);
-    const T* pb = reinterpret_cast<const T*>(ip.pb);
-    T* pc = reinterpret_cast<T*>(ip.pc);
-    if (tid < KB * NB) Bs[tid] = P::ld(pb, ob_mine);
+    if (tid < KB * NB) Bs[tid] = ldop<FL, 2>(ip.pb, ob_mine);
     uint32_t oa[R], oc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -180,12 +180,12 @@ __global__ __launch_bounds__(256) void k_wide(NodeDesc d, uint64_t ws, const int
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int k = 0; k < KB; ++k) a[r][k] = P::ld(pa, oa[r] + tak[k]);
-    const OutScale s = out_scale<P>(d, ws, ip.ai, ip.bi);
+      for (int k = 0; k < KB; ++k) a[r][k] = ldop<FL, 1>(ip.pa, oa[r] + tak[k]);
+    const OutScale s = out_scale<FL>(d, ws, ip.ai, ip.bi);
     __syncthreads();
     float mx = 0.f;
-#pragma unroll
     for (int n = 0; n < NB; ++n) {
+      const uint32_t cn = tab[TAB_CN * kTabSize + n];
       float2 b[KB];
 #pragma unroll
       for (int k = 0; k < KB; ++k) b[k] = Bs[k * NB + n];
@@ -194,28 +194,23 @@ __global__ __launch_bounds__(256) void k_wide(NodeDesc d, uint64_t ws, const int
         float2 c = make_float2(0.f, 0.f);
 #pragma unroll
         for (int k = 0; k < KB; ++k) cmac(c, a[r][k], b[k]);
-        mx = fmaxf(mx, put<P>(pc, oc[r] + tcn[n], c, s));
+        mx = fmaxf(mx, put<FL>(ip.pc, oc[r] + cn, c, s));
       }
     }
-    block_record<P>(d, ws, ip.inst, s, mx, red);
-    if constexpr (!P::kHalf) __syncthreads();  // Bs is rewritten next iteration
+    block_record<FL>(d, ws, ip.inst, s, mx, red);
+    __syncthreads();  // Bs is rewritten next iteration
   }
 }
 
-template <class P, int KB, int NB>
+template <int FL, int KB>
 __global__ __launch_bounds__(256) void k_narrow(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
-  using T = typename P::T;
   const uint32_t* __restrict__ tab = reinterpret_cast<const uint32_t*>(ws + d.tab_off);
-  uint32_t tak[KB], tcn[NB], tbk[KB], tbn[NB];
+  const int NB = 1 << d.nbits;
+  uint32_t tak[KB], tbk[KB];
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
     tak[k] = tab[TAB_AK * kTabSize + k];
     tbk[k] = tab[TAB_BK * kTabSize + k];
-  }
-#pragma unroll
-  for (int n = 0; n < NB; ++n) {
-    tcn[n] = tab[TAB_CN * kTabSize + n];
-    tbn[n] = tab[TAB_BN * kTabSize + n];
   }
   const int64_t total = d.n_inst << d.mbits;
   const uint32_t mmask = (1u << d.mbits) - 1u;
@@ -231,37 +226,33 @@ __global__ __launch_bounds__(256) void k_narrow(NodeDesc d, uint64_t ws, const i
       inst = g >> d.mbits;
       const uint32_t m = (uint32_t)g & mmask;
       const InstPtrs ip = instance_ptrs(d, ws, inst, sigma0);
-      const T* pa = reinterpret_cast<const T*>(ip.pa);
-      const T* pb = reinterpret_cast<const T*>(ip.pb);
-      T* pc = reinterpret_cast<T*>(ip.pc);
       const uint32_t oa = tab[TAB_AM * kTabSize + m];
       const uint32_t oc = tab[TAB_CM * kTabSize + m];
       float2 a[KB];
 #pragma unroll
-      for (int k = 0; k < KB; ++k) a[k] = P::ld(pa, oa + tak[k]);
-      s = out_scale<P>(d, ws, ip.ai, ip.bi);
-#pragma unroll
+      for (int k = 0; k < KB; ++k) a[k] = ldop<FL, 1>(ip.pa, oa + tak[k]);
+      s = out_scale<FL>(d, ws, ip.ai, ip.bi);
       for (int n = 0; n < NB; ++n) {
+        const uint32_t bn = tab[TAB_BN * kTabSize + n];
         float2 c = make_float2(0.f, 0.f);
 #pragma unroll
-        for (int k = 0; k < KB; ++k) cmac(c, a[k], P::ld(pb, tbn[n] + tbk[k]));
-        mx = fmaxf(mx, put<P>(pc, oc + tcn[n], c, s));
+        for (int k = 0; k < KB; ++k) cmac(c, a[k], ldop<FL, 2>(ip.pb, bn + tbk[k]));
+        mx = fmaxf(mx, put<FL>(ip.pc, oc + tab[TAB_CN * kTabSize + n], c, s));
       }
     }
-    if constexpr (P::kHalf) {
+    if constexpr ((FL & kMixBit) != 0) {
       // lanes of one instance are contiguous; reduce within segments of a wave
       mx = segment_max(mx, seg);
       const int lane = threadIdx.x & 63;
-      if (live && (lane & (seg - 1)) == 0) record_scale<P>(d, ws, inst, s, mx, true);
+      if (live && (lane & (seg - 1)) == 0) record_scale<FL>(d, ws, inst, s, mx, true);
     }
   }
 }
 
 // large K: block = (instance, 256-wide chunk of m) or, for M < 256, one
 // instance with 256 / M groups splitting K
-template <class P, int NB>
+template <int FL, int NB>
 __global__ __launch_bounds__(256) void k_kred(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
-  using T = typename P::T;
   __shared__ uint32_t kofa[256], kofb[256];
   __shared__ float2 part[256 * NB];
   __shared__ float red[4];
@@ -290,9 +281,7 @@ __global__ __launch_bounds__(256) void k_kred(NodeDesc d, uint64_t ws, const int
     const InstPtrs ip = instance_ptrs(d, ws, blk >> chunks_sh, sigma0);
     const uint32_t chunk = (uint32_t)(blk & (((int64_t)1 << chunks_sh) - 1));
     const uint32_t m = (chunk << mb) + mloc;
-    const T* pa = reinterpret_cast<const T*>(ip.pa);
-    const T* pb = reinterpret_cast<const T*>(ip.pb);
-    T* pc = reinterpret_cast<T*>(ip.pc);
+    const uint64_t pa = ip.pa, pb = ip.pb;
     const uint32_t om = tlook(tab + TAB_AM * kTabSize, m);
     float2 acc[NB];
 #pragma unroll
@@ -303,25 +292,25 @@ __global__ __launch_bounds__(256) void k_kred(NodeDesc d, uint64_t ws, const int
       const uint32_t bb = tab[TAB_BK * kTabSize + 256 + (kh & 255u)] +
                           tab[TAB_BK * kTabSize + 512 + ((kh >> 8) & 255u)] + tab[TAB_BK * kTabSize + 768 + (kh >> 16)];
       uint32_t kl = grp;
-      for (; kl + 3 * KS < klo_n; kl += 4 * KS) {
-        float2 a[4];
+      for (; kl + 7 * KS < klo_n; kl += 8 * KS) {
+        float2 a[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) a[u] = P::ld(pa, ba + kofa[kl + u * KS]);
+        for (int u = 0; u < 8; ++u) a[u] = ldop<FL, 1>(pa, ba + kofa[kl + u * KS]);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
           const uint32_t ob = bb + kofb[kl + u * KS];
 #pragma unroll
-          for (int n = 0; n < NB; ++n) cmac(acc[n], a[u], P::ld(pb, ob + tbn[n]));
+          for (int n = 0; n < NB; ++n) cmac(acc[n], a[u], ldop<FL, 2>(pb, ob + tbn[n]));
         }
       }
       for (; kl < klo_n; kl += KS) {
-        const float2 a = P::ld(pa, ba + kofa[kl]);
+        const float2 a = ldop<FL, 1>(pa, ba + kofa[kl]);
         const uint32_t ob = bb + kofb[kl];
 #pragma unroll
-        for (int n = 0; n < NB; ++n) cmac(acc[n], a, P::ld(pb, ob + tbn[n]));
+        for (int n = 0; n < NB; ++n) cmac(acc[n], a, ldop<FL, 2>(pb, ob + tbn[n]));
       }
     }
-    const OutScale s = out_scale<P>(d, ws, ip.ai, ip.bi);
+    const OutScale s = out_scale<FL>(d, ws, ip.ai, ip.bi);
     float mx = 0.f;
     if (KS > 1) {
 #pragma unroll
@@ -340,18 +329,15 @@ __global__ __launch_bounds__(256) void k_kred(NodeDesc d, uint64_t ws, const int
     if (grp == 0) {
       const uint32_t oc = tlook(tab + TAB_CM * kTabSize, m);
 #pragma unroll
-      for (int n = 0; n < NB; ++n) mx = fmaxf(mx, put<P>(pc, oc + tcn[n], acc[n], s));
+      for (int n = 0; n < NB; ++n) mx = fmaxf(mx, put<FL>(ip.pc, oc + tcn[n], acc[n], s));
     }
-    block_record<P>(d, ws, ip.inst, s, mx, red);
-    if constexpr (!P::kHalf) {
-      if (KS > 1) __syncthreads();  // part[] is rewritten next iteration
-    }
+    block_record<FL>(d, ws, ip.inst, s, mx, red);
+    if (KS > 1) __syncthreads();  // part[] is rewritten next iteration
   }
 }
 
-template <class P>
+template <int FL>
 __global__ __launch_bounds__(256) void k_generic(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
-  using T = typename P::T;
   const uint32_t* __restrict__ tab = reinterpret_cast<const uint32_t*>(ws + d.tab_off);
   const int cb = d.mbits + d.nbits;
   const int64_t total = d.n_inst << cb;
@@ -363,100 +349,96 @@ __global__ __launch_bounds__(256) void k_generic(NodeDesc d, uint64_t ws, const 
     const uint32_t m = (uint32_t)(mn & (((uint64_t)1 << d.mbits) - 1));
     const uint32_t n = (uint32_t)(mn >> d.mbits);
     const InstPtrs ip = instance_ptrs(d, ws, inst, sigma0);
-    const T* pa = reinterpret_cast<const T*>(ip.pa);
-    const T* pb = reinterpret_cast<const T*>(ip.pb);
-    T* pc = reinterpret_cast<T*>(ip.pc);
     const uint32_t oa = tlook(tab + TAB_AM * kTabSize, m);
     const uint32_t ob = tlook(tab + TAB_BN * kTabSize, n);
     float2 c = make_float2(0.f, 0.f);
     for (uint64_t k = 0; k < kcount; ++k) {
       const uint32_t kk = (uint32_t)k;
-      cmac(c, P::ld(pa, oa + tlook(tab + TAB_AK * kTabSize, kk)), P::ld(pb, ob + tlook(tab + TAB_BK * kTabSize, kk)));
+      cmac(c, ldop<FL, 1>(ip.pa, oa + tlook(tab + TAB_AK * kTabSize, kk)),
+           ldop<FL, 2>(ip.pb, ob + tlook(tab + TAB_BK * kTabSize, kk)));
     }
-    const OutScale s = out_scale<P>(d, ws, ip.ai, ip.bi);
-    const float mx = put<P>(pc, tlook(tab + TAB_CM * kTabSize, m) + tlook(tab + TAB_CN * kTabSize, n), c, s);
-    record_scale<P>(d, ws, inst, s, mx, true);
+    const OutScale s = out_scale<FL>(d, ws, ip.ai, ip.bi);
+    const float mx = put<FL>(ip.pc, tlook(tab + TAB_CM * kTabSize, m) + tlook(tab + TAB_CN * kTabSize, n), c, s);
+    record_scale<FL>(d, ws, inst, s, mx, true);
   }
 }
 
 // ---------------------------------------------------------------------------
 // dispatch
 
-template <class P, int KB, int NB>
+template <int FL, int KB>
 static hipError_t launch_small(const NodeDesc& d, uint64_t ws, const int64_t* sig, hipStream_t st) {
   if (d.mbits >= 8) {
     // R m-chunks per lane: as many as the instance allows, up to 4 (2 when
-    // KB x NB is large, to bound registers)
-    constexpr int RMAX = (KB * NB >= 64) ? 2 : 4;
+    // K is 16, to bound registers)
+    constexpr int RMAX = KB >= 16 ? 2 : 4;
     const int extra = d.mbits - 8;
     if (RMAX >= 4 && extra >= 2) {
       const int64_t blocks = d.n_inst << (d.mbits - 10);
-      hipLaunchKernelGGL((k_wide<P, KB, NB, 4>), dim3(grid_for(blocks)), dim3(256), 0, st, d, ws, sig);
+      hipLaunchKernelGGL((k_wide<FL, KB, 4>), dim3(grid_for(blocks)), dim3(256), 0, st, d, ws, sig);
     } else if (extra >= 1) {
       const int64_t blocks = d.n_inst << (d.mbits - 9);
-      hipLaunchKernelGGL((k_wide<P, KB, NB, 2>), dim3(grid_for(blocks)), dim3(256), 0, st, d, ws, sig);
+      hipLaunchKernelGGL((k_wide<FL, KB, 2>), dim3(grid_for(blocks)), dim3(256), 0, st, d, ws, sig);
     } else {
       const int64_t blocks = d.n_inst;
-      hipLaunchKernelGGL((k_wide<P, KB, NB, 1>), dim3(grid_for(blocks)), dim3(256), 0, st, d, ws, sig);
+      hipLaunchKernelGGL((k_wide<FL, KB, 1>), dim3(grid_for(blocks)), dim3(256), 0, st, d, ws, sig);
     }
   } else {
     const int64_t blocks = ((d.n_inst << d.mbits) + 255) / 256;
-    hipLaunchKernelGGL((k_narrow<P, KB, NB>), dim3(grid_for(blocks)), dim3(256), 0, st, d, ws, sig);
+    hipLaunchKernelGGL((k_narrow<FL, KB>), dim3(grid_for(blocks)), dim3(256), 0, st, d, ws, sig);
   }
   return hipGetLastError();
 }
 
-template <class P, int KB>
-static hipError_t launch_small_n(const NodeDesc& d, uint64_t ws, const int64_t* sig, hipStream_t st) {
-  switch (d.nbits) {
-    case 0: return launch_small<P, KB, 1>(d, ws, sig, st);
-    case 1: return launch_small<P, KB, 2>(d, ws, sig, st);
-    case 2: return launch_small<P, KB, 4>(d, ws, sig, st);
-    case 3: return launch_small<P, KB, 8>(d, ws, sig, st);
-    case 4: return launch_small<P, KB, 16>(d, ws, sig, st);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <class P>
+template <int FL>
 static hipError_t launch_kred(const NodeDesc& d, uint64_t ws, const int64_t* sig, hipStream_t st) {
   const int mb = d.mbits < 8 ? d.mbits : 8;
   const int64_t blocks = d.n_inst << (d.mbits - mb);
   const dim3 g(grid_for(blocks)), b(256);
   switch (d.nbits) {
-    case 0: hipLaunchKernelGGL((k_kred<P, 1>), g, b, 0, st, d, ws, sig); break;
-    case 1: hipLaunchKernelGGL((k_kred<P, 2>), g, b, 0, st, d, ws, sig); break;
-    case 2: hipLaunchKernelGGL((k_kred<P, 4>), g, b, 0, st, d, ws, sig); break;
-    case 3: hipLaunchKernelGGL((k_kred<P, 8>), g, b, 0, st, d, ws, sig); break;
+    case 0: hipLaunchKernelGGL((k_kred<FL, 1>), g, b, 0, st, d, ws, sig); break;
+    case 1: hipLaunchKernelGGL((k_kred<FL, 2>), g, b, 0, st, d, ws, sig); break;
+    case 2: hipLaunchKernelGGL((k_kred<FL, 4>), g, b, 0, st, d, ws, sig); break;
+    case 3: hipLaunchKernelGGL((k_kred<FL, 8>), g, b, 0, st, d, ws, sig); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <class P>
-static hipError_t launch_stream_p(const NodeDesc& d, uint64_t ws, const int64_t* sig, hipStream_t st) {
+template <int FL>
+static hipError_t launch_stream_fl(const NodeDesc& d, uint64_t ws, const int64_t* sig, hipStream_t st) {
   if (d.n_inst == 0) return hipSuccess;
   if (d.kbits <= 4 && d.nbits <= 4) {
     switch (d.kbits) {
-      case 0: return launch_small_n<P, 1>(d, ws, sig, st);
-      case 1: return launch_small_n<P, 2>(d, ws, sig, st);
-      case 2: return launch_small_n<P, 4>(d, ws, sig, st);
-      case 3: return launch_small_n<P, 8>(d, ws, sig, st);
-      case 4: return launch_small_n<P, 16>(d, ws, sig, st);
+      case 0: return launch_small<FL, 1>(d, ws, sig, st);
+      case 1: return launch_small<FL, 2>(d, ws, sig, st);
+      case 2: return launch_small<FL, 4>(d, ws, sig, st);
+      case 3: return launch_small<FL, 8>(d, ws, sig, st);
+      case 4: return launch_small<FL, 16>(d, ws, sig, st);
     }
   }
-  if (d.nbits <= 3) return launch_kred<P>(d, ws, sig, st);
+  if (d.nbits <= 3) return launch_kred<FL>(d, ws, sig, st);
   const int64_t blocks = ((d.n_inst << (d.mbits + d.nbits)) + 255) / 256;
-  hipLaunchKernelGGL((k_generic<P>), dim3(grid_for(blocks)), dim3(256), 0, st, d, ws, sig);
+  hipLaunchKernelGGL((k_generic<FL>), dim3(grid_for(blocks)), dim3(256), 0, st, d, ws, sig);
   return hipGetLastError();
 }
 
 hipError_t launch_stream(const NodeDesc& d, uint64_t ws, const int64_t* sig, hipStream_t st) {
-  return launch_stream_p<C64>(d, ws, sig, st);
+  return launch_stream_fl<0>(d, ws, sig, st);
 }
 
+// complex-half plans: the storage combinations a plan produces (an FP32
+// output only comes from FP32 operands: the stem)
 hipError_t launch_stream_h(const NodeDesc& d, uint64_t ws, const int64_t* sig, hipStream_t st) {
-  return launch_stream_p<CH>(d, ws, sig, st);
+  const int fl = (d.A.half ? 1 : 0) | (d.B.half ? 2 : 0) | (d.c_half ? 4 : 0);
+  switch (fl) {
+    case 0: return launch_stream_fl<kMixBit | 0>(d, ws, sig, st);
+    case 4: return launch_stream_fl<kMixBit | 4>(d, ws, sig, st);
+    case 5: return launch_stream_fl<kMixBit | 5>(d, ws, sig, st);
+    case 6: return launch_stream_fl<kMixBit | 6>(d, ws, sig, st);
+    case 7: return launch_stream_fl<kMixBit | 7>(d, ws, sig, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace matnc

@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstring>
 #include <exception>
 #include <limits>
@@ -81,6 +82,11 @@ int guarded(F&& f) {
 }
 
 constexpr uint64_t kAlign = 256;
+
+// bytes per stored element of node v: complex64 (8) unless the plan is
+// complex-half and v is an FP16-stored branch tensor (4)
+inline uint64_t eb_of(const Plan& P, int v) { return P.nodes[v].half_store ? 4 : 8; }
+
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // ---------------------------------------------------------------------------
@@ -217,7 +223,20 @@ void build_steps(Plan& P) {
   P.cmac_single = P.cmac_multi = P.cmac_inv = P.cmac_total = 0;
   P.bytes_slice = P.bytes_inv = 0;
   const double nsl = std::ldexp(1.0, (int)P.sliced.size());
-  const double eb = P.elem_bytes;
+  // complex-half storage policy: FP16 with per-instance exponents for the
+  // tensors of the twig, whose reuse width is at least a quarter of the
+  // distinct bitstrings -- that is where the bytes move, and each instance
+  // feeds only a few amplitudes, so rounding errors stay independent across
+  // amplitudes instead of shifting the whole batch (and its XEB) together.
+  // Leaves, the stem and the narrow part of the branch stay FP32.
+  for (int v = 0; v < P.n_nodes; ++v) {
+    const int64_t w = (int64_t)P.nodes[v].keys.size();
+    P.nodes[v].half_store = P.precision == MATNC_CHALF && v >= nt && w > 1 && 4 * w >= P.n_unique;
+  }
+  for (int v = nt; v < P.n_nodes; ++v) {
+    PNode& V = P.nodes[v];
+    V.rec_max = P.precision == MATNC_CHALF && !V.half_store && V.parent >= 0 && P.nodes[V.parent].half_store;
+  }
   for (int v = nt; v < P.n_nodes; ++v) {
     PNode& V = P.nodes[v];
     const PNode& ca = P.nodes[V.a];
@@ -246,12 +265,23 @@ void build_steps(Plan& P) {
     V.cfg = -1;
     if (nb + kb > 8) {
       // MFMA tiles: prefer the widest N tile that fits
-      const int order[] = {1, 0, 3, 2};
-      for (int c : order) {
-        if (mfma_config_fits(c, mb, nb, kb)) {
-          V.kernel = 1;
-          V.cfg = c;
-          break;
+      if (!V.half_store) {
+        const int order[] = {1, 0, 3, 2};
+        for (int c : order) {
+          if (mfma_config_fits(c, mb, nb, kb)) {
+            V.kernel = 1;
+            V.cfg = c;
+            break;
+          }
+        }
+      } else {
+        const int order[] = {0, 1, 3, 2};
+        for (int c : order) {
+          if (mfma_h_config_fits(c, mb, nb, kb)) {
+            V.kernel = 1;
+            V.cfg = c;
+            break;
+          }
         }
       }
     }
@@ -260,9 +290,9 @@ void build_steps(Plan& P) {
     const double w = (double)V.keys.size();
     P.cmac_single += cm;
     P.cmac_multi += w * cm;
-    const double by = eb * (w * std::ldexp(1.0, (int)V.idx.size()) +
-                            (double)A.keys.size() * std::ldexp(1.0, (int)A.idx.size()) +
-                            (double)B.keys.size() * std::ldexp(1.0, (int)B.idx.size()));
+    const double by = (double)eb_of(P, v) * w * std::ldexp(1.0, (int)V.idx.size()) +
+                      (double)eb_of(P, V.swap ? V.b : V.a) * (double)A.keys.size() * std::ldexp(1.0, (int)A.idx.size()) +
+                      (double)eb_of(P, V.swap ? V.a : V.b) * (double)B.keys.size() * std::ldexp(1.0, (int)B.idx.size());
     if (V.dep) {
       P.cmac_total += w * cm * nsl;
       P.bytes_slice += by;
@@ -331,8 +361,30 @@ void build_memory(Plan& P) {
     PNode& L = P.nodes[l];
     L.inst_elems = 1ull << L.idx.size();
     L.off = off;
-    L.buf_bytes = (uint64_t)L.keys.size() * (1ull << L.sl_bits.size()) * L.inst_elems * P.elem_bytes;
+    L.buf_bytes = (uint64_t)L.keys.size() * (1ull << L.sl_bits.size()) * L.inst_elems * 8;
     off = align_up(off + L.buf_bytes);
+  }
+  if (P.precision == MATNC_CHALF) {
+    const uint64_t hs = sizeof(HalfScale);
+    for (int l = 0; l < nt; ++l) {
+      PNode& L = P.nodes[l];
+      L.scale_off = off;
+      off = align_up(off + (uint64_t)L.keys.size() * (1ull << L.sl_bits.size()) * hs);
+    }
+    P.inv_scale_lo = off;
+    for (int v : P.prologue) {
+      P.nodes[v].scale_off = off;
+      off += (uint64_t)P.nodes[v].keys.size() * hs;
+    }
+    off = align_up(off);
+    P.inv_scale_hi = off;
+    P.dep_scale_lo = off;
+    for (int v : P.loop) {
+      P.nodes[v].scale_off = off;
+      off += (uint64_t)P.nodes[v].keys.size() * P.batch * hs;
+    }
+    off = align_up(off);
+    P.dep_scale_hi = off;
   }
   P.static_bytes = off;
 
@@ -342,7 +394,7 @@ void build_memory(Plan& P) {
     PNode& V = P.nodes[v];
     V.inst_elems = 1ull << V.idx.size();
     const uint64_t ninst = (uint64_t)V.keys.size() * (V.dep ? (uint64_t)P.batch : 1ull);
-    V.buf_bytes = align_up(ninst * V.inst_elems * P.elem_bytes);
+    V.buf_bytes = align_up(ninst * V.inst_elems * eb_of(P, v));
     int t1;
     if (v == root)
       t1 = t_end;
@@ -378,6 +430,8 @@ void build_memory(Plan& P) {
   P.workspace_bytes = align_up(P.static_bytes + arena);
 }
 
+// writes leaf l's variants (and, for complex-half, its scales) into the
+// static-region image dst (indexed by workspace offsets)
 void fill_leaf_data(Plan& P, int l, unsigned char* dst) {
   const Network& N = P.net;
   const PNode& L = P.nodes[l];
@@ -410,6 +464,7 @@ void fill_leaf_data(Plan& P, int l, unsigned char* dst) {
   uint64_t inst = 0;
   for (size_t u = 0; u < L.keys.size(); ++u) {
     for (uint64_t sv = 0; sv < nsv; ++sv, ++inst) {
+      float smx = 0.f;
       for (uint64_t e = 0; e < ne; ++e) {
         uint64_t flat = 0;
         for (int a = 0; a < r; ++a) {
@@ -424,11 +479,18 @@ void fill_leaf_data(Plan& P, int l, unsigned char* dst) {
         }
         const double re = src[2 * flat], im = src[2 * flat + 1];
         const uint64_t d = inst * ne + e;
-        if (P.elem_bytes == 8) {
-          float* f = reinterpret_cast<float*>(dst) + 2 * d;
-          f[0] = (float)re;
-          f[1] = (float)im;
-        }
+        float* f = reinterpret_cast<float*>(dst + L.off) + 2 * d;
+        f[0] = (float)re;
+        f[1] = (float)im;
+        smx = std::max(smx, std::max(std::fabs(f[0]), std::fabs(f[1])));
+      }
+      if (P.precision == MATNC_CHALF) {
+        // leaves stay FP32 (exponent 0); their maximum feeds the scale
+        // choice of FP16 consumers
+        HalfScale hs;
+        hs.e = 0;
+        std::memcpy(&hs.mx, &smx, 4);
+        std::memcpy(dst + L.scale_off + inst * sizeof(HalfScale), &hs, sizeof(hs));
       }
     }
   }
@@ -439,8 +501,10 @@ OpDesc operand_desc(const Plan& P, int child, uint64_t gmap_off) {
   OpDesc o;
   std::memset(&o, 0, sizeof(o));
   o.off = C.off;
-  o.inst_bytes = C.inst_elems * P.elem_bytes;
+  o.inst_bytes = C.inst_elems * eb_of(P, child);
+  o.half = C.half_store ? 1 : 0;
   o.gmap_off = gmap_off;
+  o.scale_off = C.scale_off;
   o.w_child = (int32_t)C.keys.size();
   const bool leaf = child < P.net.n_tensors;
   o.dep = (!leaf && C.dep) ? 1 : 0;
@@ -459,8 +523,10 @@ NodeDesc node_desc(const Plan& P, int v, int nb) {
   d.A = operand_desc(P, ca, V.ga_off);
   d.B = operand_desc(P, cb, V.gb_off);
   d.c_off = V.off;
-  d.c_inst_bytes = V.inst_elems * P.elem_bytes;
+  d.c_inst_bytes = V.inst_elems * eb_of(P, v);
+  d.c_half = V.half_store ? 1 : 0;
   d.tab_off = V.tab_off;
+  d.c_scale_off = V.scale_off;
   d.w = (int32_t)V.keys.size();
   d.dep = V.dep ? 1 : 0;
   d.n_inst = (int64_t)d.w * (V.dep ? nb : 1);
@@ -480,14 +546,27 @@ void launch_node(const Plan& P, const PNode& V, const NodeDesc& d, hipStream_t s
   hipError_t e;
   if (P.precision == MATNC_C64) {
     e = V.kernel == 1 ? launch_mfma(d, V.cfg, P.ws, sig, st) : launch_stream(d, P.ws, sig, st);
+  } else if (V.kernel == 1) {
+    e = V.half_store ? launch_mfma_h(d, V.cfg, P.ws, sig, st)
+        : V.rec_max  ? launch_mfma_rec(d, V.cfg, P.ws, sig, st)
+                     : launch_mfma(d, V.cfg, P.ws, sig, st);
   } else {
-    e = V.kernel == 1 ? launch_mfma_h(d, V.cfg, P.ws, sig, st) : launch_stream_h(d, P.ws, sig, st);
+    // FP32 tensors whose maximum nobody reads take the complex64 kernels
+    e = (V.half_store || V.rec_max) ? launch_stream_h(d, P.ws, sig, st) : launch_stream(d, P.ws, sig, st);
   }
   hip_check(e, "kernel launch");
 }
 
 void launch_batch(const Plan& P, int nb, hipStream_t st) {
+  if (P.precision == MATNC_CHALF)
+    hip_check(launch_zero(P.ws + P.dep_scale_lo, P.dep_scale_hi - P.dep_scale_lo, st), "clear scales");
   for (int v : P.loop) launch_node(P, P.nodes[v], node_desc(P, v, nb), st);
+}
+
+void launch_prologue(const Plan& P, hipStream_t st) {
+  if (P.precision == MATNC_CHALF)
+    hip_check(launch_zero(P.ws + P.inv_scale_lo, P.inv_scale_hi - P.inv_scale_lo, st), "clear scales");
+  for (int v : P.prologue) launch_node(P, P.nodes[v], node_desc(P, v, 1), st);
 }
 
 void release_graph(Plan& P) {
@@ -665,12 +744,16 @@ int matnc_plan_set_tensor(matnc_plan plan, int t, const double* data_c128) {
     P.net.data[t].assign(data_c128, data_c128 + 2 * ne);
     if (P.bound) {
       const PNode& L = P.nodes[t];
-      std::vector<unsigned char> tmp(L.buf_bytes);
-      fill_leaf_data(P, t, tmp.data());
-      std::memcpy(P.staging.data() + L.off, tmp.data(), L.buf_bytes);
+      fill_leaf_data(P, t, P.staging.data());
       hip_check(hipMemcpyAsync(reinterpret_cast<void*>(P.ws + L.off), P.staging.data() + L.off, L.buf_bytes,
                                hipMemcpyHostToDevice, P.stream),
                 "upload tensor");
+      if (P.precision == MATNC_CHALF) {
+        const uint64_t sb = (uint64_t)L.keys.size() * (1ull << L.sl_bits.size()) * sizeof(HalfScale);
+        hip_check(hipMemcpyAsync(reinterpret_cast<void*>(P.ws + L.scale_off), P.staging.data() + L.scale_off, sb,
+                                 hipMemcpyHostToDevice, P.stream),
+                  "upload tensor scales");
+      }
       hip_check(hipStreamSynchronize(P.stream), "upload tensor");
     }
     P.inv_valid = false;
@@ -708,7 +791,7 @@ int matnc_plan_bind(matnc_plan plan, void* dev_workspace, size_t bytes, void* hi
       std::memcpy(P.staging.data() + V.gb_off, V.gb.data(), V.gb.size() * 4);
     }
     std::memcpy(P.staging.data() + P.rootmap_off, P.rootmap.data(), P.rootmap.size() * 4);
-    for (int l = 0; l < nt; ++l) fill_leaf_data(P, l, P.staging.data() + P.nodes[l].off);
+    for (int l = 0; l < nt; ++l) fill_leaf_data(P, l, P.staging.data());
     hip_check(hipMemcpyAsync(dev_workspace, P.staging.data(), P.static_bytes, hipMemcpyHostToDevice, P.stream),
               "upload static region");
     hip_check(hipStreamSynchronize(P.stream), "upload static region");
@@ -743,7 +826,7 @@ int matnc_execute(matnc_plan plan, int64_t slice_begin, int64_t slice_end, doubl
     int64_t* sig = reinterpret_cast<int64_t*>(P.ws + P.sigma_off);
     if (!P.inv_valid) {
       hip_check(launch_set_i64(sig, 0, st), "set sigma");
-      for (int v : P.prologue) launch_node(P, P.nodes[v], node_desc(P, v, 1), st);
+      launch_prologue(P, st);
       P.inv_valid = true;
     }
     const OpDesc root = root_desc(P);
@@ -813,6 +896,10 @@ int matnc_plan_profile(matnc_plan plan, int64_t slice_begin, int nb, float* time
     hipStream_t st = P.stream;
     int64_t* sig = reinterpret_cast<int64_t*>(P.ws + P.sigma_off);
     hip_check(launch_set_i64(sig, 0, st), "set sigma");
+    if (P.precision == MATNC_CHALF) {
+      hip_check(launch_zero(P.ws + P.inv_scale_lo, P.inv_scale_hi - P.inv_scale_lo, st), "clear scales");
+      hip_check(launch_zero(P.ws + P.dep_scale_lo, P.dep_scale_hi - P.dep_scale_lo, st), "clear scales");
+    }
     for (size_t i = 0; i < order.size(); ++i) {
       const int v = order[i];
       const PNode& V = P.nodes[v];
@@ -830,7 +917,6 @@ int matnc_plan_profile(matnc_plan plan, int64_t slice_begin, int nb, float* time
       cmac[j] = 0;
       bytes[j] = 0;
     }
-    const double eb = P.elem_bytes;
     for (size_t i = 0; i < order.size(); ++i) {
       const int v = order[i];
       const PNode& V = P.nodes[v];
@@ -845,8 +931,9 @@ int matnc_plan_profile(matnc_plan plan, int64_t slice_begin, int nb, float* time
       const PNode& B = P.nodes[V.swap ? V.a : V.b];
       const double ia = (double)A.keys.size() * (A.dep ? (V.dep ? nb : 1) : 1);
       const double ib = (double)B.keys.size() * (B.dep ? (V.dep ? nb : 1) : 1);
-      bytes[j] = eb * (inst * std::ldexp(1.0, (int)V.idx.size()) + ia * std::ldexp(1.0, (int)A.idx.size()) +
-                       ib * std::ldexp(1.0, (int)B.idx.size()));
+      bytes[j] = (double)eb_of(P, v) * inst * std::ldexp(1.0, (int)V.idx.size()) +
+                 (double)eb_of(P, V.swap ? V.b : V.a) * ia * std::ldexp(1.0, (int)A.idx.size()) +
+                 (double)eb_of(P, V.swap ? V.a : V.b) * ib * std::ldexp(1.0, (int)B.idx.size());
     }
   });
 }

@@ -47,6 +47,8 @@ struct PNode {
   std::vector<int> sl_index;     // the sliced index ids, same order
   // step description (internal nodes)
   bool swap = false;             // true: operand A is child b
+  bool half_store = false;       // complex-half plans: stored as FP16 (twig tensors)
+  bool rec_max = false;          // complex-half plans: FP32 tensor whose maximum an FP16 consumer needs
   int kernel = 0;                // 0 streaming, 1 MFMA
   int cfg = -1;
   std::vector<int> M, N, K;      // virtual orders of the three index classes
@@ -56,7 +58,7 @@ struct PNode {
   uint64_t off = 0;              // byte offset in workspace
   uint64_t tab_off = 0, ga_off = 0, gb_off = 0;
   int time = 0;                  // schedule position
-  int64_t exps_off = 0;          // chalf: byte offset of per-instance exponents
+  uint64_t scale_off = 0;        // complex-half: byte offset of the HalfScale array
 };
 
 struct Plan {
@@ -73,6 +75,8 @@ struct Plan {
   std::vector<PNode> nodes;
   std::vector<int32_t> rootmap;
   uint64_t rootmap_off = 0;
+  uint64_t inv_scale_lo = 0, inv_scale_hi = 0;  // complex-half scale slots of invariant nodes
+  uint64_t dep_scale_lo = 0, dep_scale_hi = 0;  // ... and of per-batch nodes
   uint64_t sigma_off = 0;
   uint64_t static_bytes = 0;
   uint64_t workspace_bytes = 0;

@@ -1,0 +1,128 @@
+"""Complex-half path (FP16 storage + per-instance exponents, FP16 MFMA, FP32
+accumulation, FP64 slice-sum) against the FP64 oracle.
+
+Bar: ||a - a_ref|| / ||a_ref|| <= 3e-3 over the batch and |XEB - XEB_ref|
+<= 1e-4.  FP16 storage is used for the tensors of the twig (reuse width at
+least a quarter of the distinct bitstrings); leaves, stem and the narrow
+branch stay FP32.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import rel_err, require_gpu, say
+from oracle import closed_forms, statevector, xeb as oxeb
+from workload import CONFIGS, GridSpec, permutation_circuit, random_circuit, sub_instance_c4, uniform_bitstrings
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def contraction(circ, words, open_qubits=(), cap=None, batch=1, trials=8):
+    from paper_2212_04749_amd import api
+    return api.Contraction.from_circuit(circ, words, open_qubits=open_qubits, cap=cap, precision="chalf",
+                                        slice_batch=batch, trials=trials)
+
+
+def xeb_of(a, n):
+    return float(np.ldexp(np.mean(np.abs(a) ** 2), n) - 1)
+
+
+def test_chalf_c1_and_sliced():
+    require_gpu()
+    w = CONFIGS["C1"]
+    circ, words = w.circuit(), w.bitstrings()
+    ref = statevector.amplitudes(circ, words)
+    say("chalf C1")
+    run = contraction(circ, words)
+    got = run.amplitudes()
+    e1 = rel_err(got, ref)
+    f = run.xeb()
+    run.close()
+    say(f"chalf C1 rel err {e1:.2e} xeb err {abs(f - oxeb.linear_xeb(ref, 16)):.2e}")
+    assert e1 <= 3e-3
+    assert abs(f - oxeb.linear_xeb(ref, 16)) <= 1e-4
+    say("chalf C1 sliced cap 12")
+    run = contraction(circ, words, cap=12, batch=4)
+    assert run.n_slices >= 4
+    got = run.amplitudes()
+    run.close()
+    assert rel_err(got, ref) <= 3e-3
+
+
+def test_chalf_open_legs():
+    require_gpu()
+    circ = random_circuit(GridSpec(3, 4), 7, 8)
+    opens = (1, 6, 10)
+    words = uniform_bitstrings(12, 20, 9)
+    psi = statevector.final_state(circ)
+    say("chalf open legs")
+    run = contraction(circ, words, open_qubits=opens, cap=9)
+    got = run.amplitudes()
+    run.close()
+    ref = np.zeros_like(got)
+    for i, w0 in enumerate(words):
+        for j in range(8):
+            word = int(w0)
+            for t, q in enumerate(opens):
+                word = (word & ~(1 << q)) | (((j >> t) & 1) << q)
+            ref[i, j] = statevector.amplitudes_from_state(psi, [word])[0]
+    assert rel_err(got, ref) <= 3e-3
+
+
+def test_chalf_c4_sub_instance():
+    """The 20-qubit, depth-14 instance on which the precision error is stated,
+    sliced to 64 slices (cap = greedy max rank - 6), 1024 bitstrings."""
+    require_gpu()
+    from paper_2212_04749_amd import planner
+    from paper_2212_04749_amd.circuit_tn import build_network
+    w = sub_instance_c4()
+    g = json.load(open(os.path.join(GOLDEN, "c4_sub.json")))
+    circ, words = w.circuit(), w.bitstrings()
+    assert [str(int(x)) for x in words] == g["words"]
+    ref = np.array([complex(a, b) for a, b in g["amps"]])
+    net = build_network(circ)
+    full = planner.find_plan(net, words, (), None, trials=8)
+    cap = full.costs.max_rank - 6
+    say(f"chalf C4 sub-instance cap {cap}")
+    run = contraction(circ, words, cap=cap, batch=8)
+    got = run.amplitudes()
+    run.close()
+    err = rel_err(got, ref)
+    say(f"chalf C4 sub rel err {err:.2e} slices {run.n_slices} xeb err {abs(xeb_of(got, 20) - xeb_of(ref, 20)):.2e}")
+    assert err <= 3e-3
+    assert abs(xeb_of(got, 20) - xeb_of(ref, 20)) <= 1e-4
+
+
+def test_chalf_c2_against_stored_oracle():
+    require_gpu()
+    w = CONFIGS["C2"]
+    g = json.load(open(os.path.join(GOLDEN, "c2_subset.json")))
+    circ, words = w.circuit(), w.bitstrings()
+    idx = np.array(g["indices"])
+    ref = np.array([complex(a, b) for a, b in g["amps"]])
+    say("chalf C2 full config")
+    run = contraction(circ, words, cap=28, batch=4, trials=4)
+    got = run.amplitudes()[idx]
+    run.close()
+    err = rel_err(got, ref)
+    say(f"chalf C2 rel err {err:.2e} xeb err {abs(xeb_of(got, 30) - xeb_of(ref, 30)):.2e}")
+    assert err <= 3e-3
+    assert abs(xeb_of(got, 30) - xeb_of(ref, 30)) <= 1e-4
+
+
+def test_chalf_permutation_scaling_c2_size():
+    """|a| = 2^-15 for every bitstring: exercises the exponent bookkeeping."""
+    require_gpu()
+    w = CONFIGS["C2"]
+    circ = permutation_circuit(w.grid, w.depth, 77)
+    words = uniform_bitstrings(30, 512, 78)
+    say("chalf permutation 5x6 d12")
+    run = contraction(circ, words, cap=28, batch=2, trials=4)
+    got = run.amplitudes()
+    run.close()
+    ref = closed_forms.permutation_amplitudes(circ, words)
+    assert rel_err(got, ref) <= 3e-3
