@@ -47,6 +47,7 @@ def parse():
     p.add_argument("--slice-batch", type=int, default=0, help="0 = workload default")
     p.add_argument("--trials", type=int, default=32, help="order-search candidates")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-autotune", action="store_true", help="keep the heuristic MFMA tile choice")
     p.add_argument("--profile-out", default="", help="write the per-step profile as JSON")
     return p.parse_args()
 
@@ -185,8 +186,13 @@ def main():
     run = api.Contraction(net, spec, words, precision=args.precision, slice_batch=batch)
     torch.cuda.synchronize()
     t_bind = time.perf_counter() - t0
+    t_tune = 0.0
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        run.autotune(reps=2)
+        t_tune = time.perf_counter() - t0
     info = run.info
-    log(f"plan {t_plan:.2f}s bind {t_bind:.2f}s workspace {info.workspace_bytes / 2**30:.2f} GiB "
+    log(f"plan {t_plan:.2f}s bind {t_bind:.2f}s autotune {t_tune:.2f}s workspace {info.workspace_bytes / 2**30:.2f} GiB "
         f"slices {info.n_slices} cmac_total {info.cmac_total:.3e}")
 
     amps = run.new_amplitudes()
@@ -254,6 +260,7 @@ def main():
         "error_vs_fp64": err,
         "plan_s": t_plan,
         "bind_s": t_bind,
+        "autotune_s": t_tune,
         "config": workload_description(name, w, info, spec) | {"slice_batch": batch, "precision": args.precision},
         "roofline": roof,
         "cpu_baseline": cpu,

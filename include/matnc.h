@@ -178,6 +178,19 @@ int matnc_xeb(matnc_plan plan, const double *amps_dev, double *xeb_dev);
 int matnc_plan_destroy(matnc_plan plan);
 
 /*
+ * matnc_plan_autotune -- choose the tile configuration of every step that
+ * runs on the MFMA kernel by timing each configuration that fits the step's
+ * shape (reps launches each, HIP events on the bound stream) and keeping the
+ * fastest; then re-capture the graph.  Choices are keyed by shape class
+ * (precision, m/n/k bits, instance count rounded to a power of two) and, if
+ * cache_path is not NULL, read from and written back to that JSON file
+ * (classes already in the file are not re-timed).  Overwrites intermediate
+ * tensors (the stem cache is recomputed at the next execute).  Waits for the
+ * stream.  Errors: MATNC_E_STATE (not bound), MATNC_E_HIP, MATNC_E_INVALID.
+ */
+int matnc_plan_autotune(matnc_plan plan, int reps, const char *cache_path);
+
+/*
  * matnc_plan_reset_cache -- drop the slice-invariant tensors (stem cache)
  * so that the next matnc_execute recomputes them; used to time a complete
  * pass.  No device work is queued.  Errors: MATNC_E_INVALID (null plan).
@@ -208,7 +221,10 @@ int matnc_plan_profile(matnc_plan plan, int64_t slice_begin, int nb, float *time
  * amplitude buffer and one XEB slot per plan.
  *   matnc_queue_execute(q, amps_dev[n], xeb_dev[n]) contracts every slice
  *   of every plan (adding into amps_dev[i]) and writes XEB of plan i to
- *   xeb_dev[i].  All plans must be bound to the same stream.
+ *   xeb_dev[i].  All plans must be bound to the same (non-null) stream.  The
+ *   whole queue -- every plan's stem, slice batches, slice-sums and XEB --
+ *   is captured once as a single HIP graph (re-captured when the buffers or
+ *   a plan's binding change) and launched as one graph per call.
  */
 int matnc_queue_create(int n_plans, const matnc_plan *plans, matnc_queue *out);
 int matnc_queue_execute(matnc_queue q, double *const *amps_dev, double *xeb_dev);

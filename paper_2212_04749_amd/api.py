@@ -156,6 +156,12 @@ class Contraction:
             dep.append(dep[a] or dep[b])
         return dep[len(self.net.indices):]
 
+    def autotune(self, reps: int = 3, cache_path: Optional[str] = None) -> None:
+        """Pick MFMA tile shapes by timing them (see matnc_plan_autotune);
+        cache_path defaults to $MATNC_AUTOTUNE_CACHE."""
+        import os
+        B.matnc_plan_autotune(self._plan, reps, cache_path or os.environ.get("MATNC_AUTOTUNE_CACHE"))
+
     def reset_cache(self) -> None:
         B.matnc_plan_reset_cache(self._plan)
 
@@ -169,11 +175,14 @@ class Contraction:
 
     def close(self):
         if getattr(self, "_plan", None):
+            if getattr(self, "stream", None) is not None:
+                self.stream.synchronize()
             B.matnc_plan_destroy(self._plan)
             self._plan = None
         if getattr(self, "_net", None):
             B.matnc_network_destroy(self._net)
             self._net = None
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -206,3 +215,34 @@ def contract_pair(A, Bt, C, pos, kernel: int = -1, stream=None):
                      pos["posB_k"], pos["posB_n"], pos["posC_m"], pos["posC_n"], kernel,
                      scratch.data_ptr(), scratch.numel(), stream.cuda_stream)
     return scratch  # keep alive until the stream has run the kernel
+
+
+class Queue:
+    """Several bound contractions executed as one captured graph (uneven
+    batches); they must share one stream."""
+
+    def __init__(self, runs):
+        self.runs = list(runs)
+        self._q = B.matnc_queue_create([r._plan for r in self.runs])
+        self.stream = self.runs[0].stream
+
+    def execute(self):
+        """Fresh zeroed amplitude buffers, one pass of every plan; returns
+        (list of amplitude tensors, XEB tensor)."""
+        import torch
+        with torch.cuda.stream(self.stream):
+            amps = [r.new_amplitudes() for r in self.runs]
+            xeb = torch.zeros(len(self.runs), dtype=torch.float64, device=self.runs[0].device)
+        B.matnc_queue_execute(self._q, [a.data_ptr() for a in amps], xeb.data_ptr())
+        return amps, xeb
+
+    def close(self):
+        if getattr(self, "_q", None):
+            B.matnc_queue_destroy(self._q)
+            self._q = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -63,6 +63,7 @@ EXPORTS = [
     "matnc_execute", "matnc_xeb", "matnc_plan_destroy", "matnc_queue_create",
     "matnc_queue_execute", "matnc_queue_destroy", "matnc_contract_scratch_bytes",
     "matnc_mfma_config_count", "matnc_contract", "matnc_plan_reset_cache", "matnc_plan_profile",
+    "matnc_plan_autotune",
 ]
 
 
@@ -93,6 +94,7 @@ def lib():
     L.matnc_queue_execute.argtypes = [c_void_p, POINTER(c_void_p), c_void_p]
     L.matnc_queue_destroy.argtypes = [c_void_p]
     L.matnc_plan_reset_cache.argtypes = [c_void_p]
+    L.matnc_plan_autotune.argtypes = [c_void_p, c_int, c_char_p]
     L.matnc_plan_profile.argtypes = [c_void_p, c_int64, c_int, POINTER(ctypes.c_float), POINTER(c_int),
                                      POINTER(c_double), POINTER(c_double)]
     L.matnc_contract_scratch_bytes.restype = c_size_t
@@ -237,3 +239,8 @@ def matnc_plan_profile(plan: int, slice_begin: int, nb: int, n_steps: int):
     b = (c_double * max(1, n_steps))()
     check(lib().matnc_plan_profile(c_void_p(plan), c_int64(slice_begin), int(nb), t, k, c, b))
     return [(t[j], k[j], c[j], b[j]) for j in range(n_steps)]
+
+
+def matnc_plan_autotune(plan: int, reps: int = 3, cache_path=None) -> None:
+    path = cache_path.encode() if cache_path else None
+    check(lib().matnc_plan_autotune(c_void_p(plan), int(reps), path))

@@ -16,6 +16,8 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <exception>
@@ -44,6 +46,9 @@ struct matnc_plan_s {
 };
 struct matnc_queue_s {
   std::vector<matnc_plan> plans;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void*> key;  // amplitude buffers, XEB slot and plan generations of the captured graph
 };
 
 namespace {
@@ -576,6 +581,88 @@ void release_graph(Plan& P) {
   P.graph = nullptr;
 }
 
+// capture one full slice batch as a graph (not possible on the null stream)
+void capture_batch_graph(Plan& P) {
+  release_graph(P);
+  ++P.generation;
+  if (P.stream == nullptr || P.loop.empty()) return;
+  hip_check(hipStreamBeginCapture(P.stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  try {
+    launch_batch(P, P.batch, P.stream);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(P.stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  hip_check(hipStreamEndCapture(P.stream, &P.graph), "end capture");
+  hip_check(hipGraphInstantiate(&P.graph_exec, P.graph, nullptr, nullptr, 0), "graph instantiate");
+}
+
+// every launch of a complete pass over slices [b, e) into amps (no graphs)
+void launch_pass(Plan& P, int64_t b, int64_t e, double* amps, hipStream_t st) {
+  int64_t* sig = reinterpret_cast<int64_t*>(P.ws + P.sigma_off);
+  hip_check(launch_set_i64(sig, 0, st), "set sigma");
+  launch_prologue(P, st);
+  const OpDesc root = root_desc(P);
+  const int64_t k = (int64_t)P.words.size();
+  const int ob = (int)P.open_qubits.size();
+  for (int64_t s0 = b; s0 < e; s0 += P.batch) {
+    const int nb = (int)std::min<int64_t>(P.batch, e - s0);
+    hip_check(launch_set_i64(sig, s0, st), "set sigma");
+    launch_batch(P, nb, st);
+    hipError_t er = P.precision == MATNC_C64 ? launch_slice_sum(root, P.ws, sig, nb, k, ob, amps, st)
+                                             : launch_slice_sum_h(root, P.ws, sig, nb, k, ob, amps, st);
+    hip_check(er, "slice sum");
+  }
+}
+
+// shape class of an MFMA step for the tuning cache
+std::string tune_key(const Plan& P, const PNode& V, int64_t n_inst) {
+  int lg = 0;
+  while ((1LL << lg) < n_inst) ++lg;
+  return std::string(P.precision == MATNC_C64 ? "c64" : "chalf") + (V.half_store ? "/h" : "/f") + "/" +
+         std::to_string(V.M.size()) + "," + std::to_string(V.N.size()) + "," + std::to_string(V.K.size()) + "/" +
+         std::to_string(lg);
+}
+
+std::map<std::string, int> read_tune_cache(const char* path) {
+  std::map<std::string, int> out;
+  if (!path) return out;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return out;
+  std::string text;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, n);
+  std::fclose(f);
+  // entries "key": integer
+  size_t pos = 0;
+  while ((pos = text.find('"', pos)) != std::string::npos) {
+    const size_t end = text.find('"', pos + 1);
+    if (end == std::string::npos) break;
+    const std::string key = text.substr(pos + 1, end - pos - 1);
+    const size_t colon = text.find(':', end);
+    if (colon == std::string::npos) break;
+    out[key] = std::atoi(text.c_str() + colon + 1);
+    pos = colon + 1;
+  }
+  return out;
+}
+
+void write_tune_cache(const char* path, const std::map<std::string, int>& m) {
+  if (!path) return;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) fail(MATNC_E_INVALID, std::string("cannot write tuning cache ") + path);
+  std::fprintf(f, "{\n");
+  size_t i = 0;
+  for (auto& kv : m) std::fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < m.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+  if (std::rename(tmp.c_str(), path) != 0) fail(MATNC_E_INVALID, std::string("cannot write tuning cache ") + path);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -797,20 +884,7 @@ int matnc_plan_bind(matnc_plan plan, void* dev_workspace, size_t bytes, void* hi
     hip_check(hipStreamSynchronize(P.stream), "upload static region");
     P.bound = true;
     P.inv_valid = false;
-    // capture one full slice batch as a graph (not possible on the null stream)
-    if (P.stream != nullptr && !P.loop.empty()) {
-      hip_check(hipStreamBeginCapture(P.stream, hipStreamCaptureModeThreadLocal), "begin capture");
-      try {
-        launch_batch(P, P.batch, P.stream);
-      } catch (...) {
-        hipGraph_t g = nullptr;
-        (void)hipStreamEndCapture(P.stream, &g);
-        if (g) (void)hipGraphDestroy(g);
-        throw;
-      }
-      hip_check(hipStreamEndCapture(P.stream, &P.graph), "end capture");
-      hip_check(hipGraphInstantiate(&P.graph_exec, P.graph, nullptr, nullptr, 0), "graph instantiate");
-    }
+    capture_batch_graph(P);
   });
 }
 
@@ -863,6 +937,75 @@ int matnc_plan_destroy(matnc_plan plan) {
     delete plan;
   }
   return MATNC_OK;
+}
+
+int matnc_plan_autotune(matnc_plan plan, int reps, const char* cache_path) {
+  return guarded([&] {
+    if (!plan) fail(MATNC_E_INVALID, "null plan");
+    Plan& P = plan->p;
+    if (!P.bound) fail(MATNC_E_STATE, "autotune before bind");
+    if (reps < 1) fail(MATNC_E_INVALID, "reps must be >= 1");
+    std::map<std::string, int> cache = read_tune_cache(cache_path);
+    hipStream_t st = P.stream;
+    int64_t* sig = reinterpret_cast<int64_t*>(P.ws + P.sigma_off);
+    hip_check(launch_set_i64(sig, 0, st), "set sigma");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hip_check(hipEventCreate(&e0), "event create");
+    hip_check(hipEventCreate(&e1), "event create");
+    struct G {
+      hipEvent_t a, b;
+      ~G() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+      }
+    } guard{e0, e1};
+    std::vector<int> order(P.prologue);
+    order.insert(order.end(), P.loop.begin(), P.loop.end());
+    for (int v : order) {
+      PNode& V = P.nodes[v];
+      if (V.kernel != 1) continue;
+      const NodeDesc d0 = node_desc(P, v, V.dep ? P.batch : 1);
+      const std::string key = tune_key(P, V, d0.n_inst);
+      auto it = cache.find(key);
+      const bool half = V.half_store;
+      const int ncfg = half ? mfma_h_config_count() : mfma_config_count();
+      if (it != cache.end()) {
+        const bool fits = half ? mfma_h_config_fits(it->second, (int)V.M.size(), (int)V.N.size(), (int)V.K.size())
+                               : mfma_config_fits(it->second, (int)V.M.size(), (int)V.N.size(), (int)V.K.size());
+        if (fits) {
+          V.cfg = it->second;
+          continue;
+        }
+      }
+      float best = 0.f;
+      int best_cfg = V.cfg;
+      bool have = false;
+      for (int c = 0; c < ncfg; ++c) {
+        const bool fits = half ? mfma_h_config_fits(c, (int)V.M.size(), (int)V.N.size(), (int)V.K.size())
+                               : mfma_config_fits(c, (int)V.M.size(), (int)V.N.size(), (int)V.K.size());
+        if (!fits) continue;
+        V.cfg = c;
+        launch_node(P, V, d0, st);  // warm-up
+        hip_check(hipEventRecord(e0, st), "event record");
+        for (int r = 0; r < reps; ++r) launch_node(P, V, d0, st);
+        hip_check(hipEventRecord(e1, st), "event record");
+        hip_check(hipEventSynchronize(e1), "event sync");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
+        if (!have || ms < best) {
+          have = true;
+          best = ms;
+          best_cfg = c;
+        }
+      }
+      V.cfg = best_cfg;
+      cache[key] = best_cfg;
+    }
+    hip_check(hipStreamSynchronize(st), "autotune sync");
+    write_tune_cache(cache_path, cache);
+    P.inv_valid = false;
+    capture_batch_graph(P);
+  });
 }
 
 int matnc_plan_reset_cache(matnc_plan plan) {
@@ -963,19 +1106,49 @@ int matnc_queue_execute(matnc_queue q, double* const* amps_dev, double* xeb_dev)
       if (i == 0) st = P.stream;
       if (P.stream != st) fail(MATNC_E_INVALID, "queue plans must share one stream");
     }
+    if (st == nullptr) fail(MATNC_E_INVALID, "queue plans must be bound to a non-null stream");
+    std::vector<const void*> key;
     for (size_t i = 0; i < q->plans.size(); ++i) {
-      matnc_plan p = q->plans[i];
-      const int64_t ns = (int64_t)1 << p->p.sliced.size();
-      int rc = matnc_execute(p, 0, ns, amps_dev[i]);
-      if (rc != MATNC_OK) fail(rc, "queue plan " + std::to_string(i) + ": " + g_err);
-      rc = matnc_xeb(p, amps_dev[i], xeb_dev + i);
-      if (rc != MATNC_OK) fail(rc, "queue plan " + std::to_string(i) + ": " + g_err);
+      if (!amps_dev[i]) fail(MATNC_E_INVALID, "null amplitude buffer in queue");
+      key.push_back(amps_dev[i]);
+      key.push_back(reinterpret_cast<const void*>(q->plans[i]->p.generation));
+      key.push_back(reinterpret_cast<const void*>(q->plans[i]->p.ws));
     }
+    key.push_back(xeb_dev);
+    if (!q->exec || key != q->key) {
+      if (q->exec) (void)hipGraphExecDestroy(q->exec);
+      if (q->graph) (void)hipGraphDestroy(q->graph);
+      q->exec = nullptr;
+      q->graph = nullptr;
+      hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin queue capture");
+      try {
+        for (size_t i = 0; i < q->plans.size(); ++i) {
+          Plan& P = q->plans[i]->p;
+          launch_pass(P, 0, (int64_t)1 << P.sliced.size(), amps_dev[i], st);
+          const int64_t count = (int64_t)P.words.size() << P.open_qubits.size();
+          hip_check(launch_xeb(amps_dev[i], count, P.net.n_qubits, xeb_dev + i, st), "xeb");
+        }
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(st, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      hip_check(hipStreamEndCapture(st, &q->graph), "end queue capture");
+      hip_check(hipGraphInstantiate(&q->exec, q->graph, nullptr, nullptr, 0), "queue graph instantiate");
+      q->key = key;
+    }
+    hip_check(hipGraphLaunch(q->exec, st), "queue graph launch");
+    for (auto p : q->plans) p->p.inv_valid = true;
   });
 }
 
 int matnc_queue_destroy(matnc_queue q) {
-  delete q;
+  if (q) {
+    if (q->exec) (void)hipGraphExecDestroy(q->exec);
+    if (q->graph) (void)hipGraphDestroy(q->graph);
+    delete q;
+  }
   return MATNC_OK;
 }
 

@@ -96,6 +96,7 @@ struct Plan {
   hipStream_t stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  uint64_t generation = 0;             // bumped whenever launch parameters change
   std::vector<unsigned char> staging;  // host image of the static region
   std::vector<NodeDesc> descs;         // per node (full-batch instance counts)
 };

@@ -26,9 +26,10 @@ deterministic greedy order (contract the connected pair minimising
 size(out) - size(A) - size(B), ties to the smaller CMAC and then the lowest
 id pair) is also available and is one of the candidates.
 
-Slicer: while some tensor is over the cap, slice the index that minimises the
-total cost (slice-invariant nodes once, the rest times 2^|S|), ties to the
-lowest index id.
+Slicer: while some tensor is over the cap, slice the index that most
+reduces the total rank overflow above the cap (sum over tensors of
+rank - cap), then the one with the lowest total cost (slice-invariant nodes
+once, the rest times 2^|S|), ties to the lowest index id.
 """
 
 from __future__ import annotations
@@ -317,8 +318,9 @@ def slice_to_cap(st: Structure, pairs: Sequence[Tuple[int, int]], w: Sequence[in
                  cap: Optional[int], min_slices: int = 0,
                  max_sliced: int = 40) -> Tuple[List[int], Costs]:
     """Slicer: while max rank > cap (or fewer than min_slices indices are
-    sliced), add the index minimising the total cost, ties to the lowest id.
-    Open output indices are never sliced."""
+    sliced), add the index that most reduces the rank overflow above the
+    cap, then minimises the total cost, ties to the lowest id.  Open output
+    indices are never sliced."""
     sliced_mask = 0
     chosen: List[int] = []
     tree = build_tree(st, pairs, 0)
@@ -344,8 +346,9 @@ def slice_to_cap(st: Structure, pairs: Sequence[Tuple[int, int]], w: Sequence[in
             trial_mask = sliced_mask | (1 << i)
             t2 = build_tree(st, pairs, trial_mask)
             c = costs(st, t2, w, trial_mask)
-            over = max(m.bit_count() for m in t2.masks)
-            key = (c.total * (1.0 + 0.0 * over), i)
+            # first shrink the total rank overflow above the cap, then cost
+            over = 0 if cap is None else sum(max(0, m.bit_count() - cap) for m in t2.masks)
+            key = (over, c.total, i)
             if best is None or key < best[0]:
                 best = (key, i)
         if best is None:
@@ -395,7 +398,8 @@ def refine(st: Structure, plan: Plan, words: np.ndarray, cap: Optional[int],
 def find_plan(net: TensorNetwork, words: np.ndarray, open_qubits: Sequence[int] = (),
               cap: Optional[int] = None, seed: int = 0, trials: int = 64,
               min_slices: int = 0, exact_slices: Optional[int] = None,
-              include_greedy: bool = True, refine_top: int = 3) -> Plan:
+              include_greedy: bool = True, refine_top: int = 3, partition_trials: int = 0,
+              rgreedy_trials: int = 0) -> Plan:
     """Search candidate orders; slice each to the cap; refine the cheapest
     few by subtree reconfiguration; keep the cheapest."""
     st = Structure.from_network(net, open_qubits)
@@ -410,6 +414,14 @@ def find_plan(net: TensorNetwork, words: np.ndarray, open_qubits: Sequence[int] 
         temp = float(rng.uniform(0.0, 1.0))
         temp2 = float(rng.uniform(0.0, 0.5)) if t % 2 else 0.0
         candidates.append((f"stem-branch[{t}]", stem_branch_pairs(st, k_eff, rng, alpha, temp, temp2)))
+    for t in range(rgreedy_trials):
+        alpha = float(rng.uniform(0.0, 1.5))
+        temp = float(rng.uniform(0.0, 1.0))
+        candidates.append((f"rgreedy[{t}]",
+                           _greedy(st, list(range(st.n_tensors)), st.leaf_masks, rng, alpha, temp)[0]))
+    for t in range(partition_trials):
+        imb = float(rng.uniform(0.05, 0.35))
+        candidates.append((f"bisection[{t}]", partition_pairs(st, rng, imb)))
     scored = []
     for name, pairs in candidates:
         tree = build_tree(st, pairs)
@@ -605,3 +617,178 @@ def reconfigure(st: Structure, pairs, words, cap: Optional[int], sliced_mask: in
         if not changed:
             break
     return T.to_pairs()
+
+
+# --------------------------------------------------------------------------
+# recursive bisection
+#
+# Partition-based order search: split the tensors into two balanced halves
+# that share as few indices as possible, contract each half recursively and
+# join them; small groups are ordered exactly by the subset DP above.  A
+# split starts from a region grown breadth-first from a random tensor and is
+# improved by Fiduccia-Mattheyses passes (move the unlocked tensor whose move
+# cuts the most shared indices, keep the best prefix of the pass).  The
+# paper searches orders with hypergraph partitioning (KaHyPar) under the
+# multi-amplitude loss; this is a small self-contained stand-in, with the
+# loss applied afterwards by subtree reconfiguration.
+
+
+def _fm_bisect(nodes: List[int], nbrs: Dict[int, Dict[int, int]], rng, imbalance: float) -> Tuple[set, set]:
+    n = len(nodes)
+    node_set = set(nodes)
+    target = n // 2
+    lo = max(1, int(n * (0.5 - imbalance)))
+    hi = min(n - 1, int(math.ceil(n * (0.5 + imbalance))))
+    # BFS-grown initial region
+    start = nodes[int(rng.integers(0, n))]
+    left = {start}
+    frontier = [start]
+    while len(left) < target:
+        nxt = []
+        for u in frontier:
+            for v in nbrs[u]:
+                if v in node_set and v not in left:
+                    left.add(v)
+                    nxt.append(v)
+                    if len(left) >= target:
+                        break
+            if len(left) >= target:
+                break
+        if not nxt:
+            rest = [v for v in nodes if v not in left]
+            if not rest:
+                break
+            nxt = [rest[int(rng.integers(0, len(rest)))]]
+            left.add(nxt[0])
+        frontier = nxt
+    side = {v: (0 if v in left else 1) for v in nodes}
+
+    def cut_of():
+        c = 0
+        for u in nodes:
+            for v, wgt in nbrs[u].items():
+                if v in node_set and u < v and side[u] != side[v]:
+                    c += wgt
+        return c
+
+    best_cut = cut_of()
+    for _ in range(8):
+        gain = {}
+        for u in nodes:
+            g = 0
+            for v, wgt in nbrs[u].items():
+                if v in node_set:
+                    g += wgt if side[v] != side[u] else -wgt
+            gain[u] = g
+        locked = set()
+        size0 = sum(1 for v in nodes if side[v] == 0)
+        cur = best_cut
+        moves = []
+        best_prefix, best_val = 0, best_cut
+        for _step in range(n):
+            cand = None
+            for u in nodes:
+                if u in locked:
+                    continue
+                s0 = size0 - 1 if side[u] == 0 else size0 + 1
+                if s0 < lo or s0 > hi:
+                    continue
+                key = (gain[u], rng.random())
+                if cand is None or key > cand[0]:
+                    cand = (key, u)
+            if cand is None:
+                break
+            u = cand[1]
+            locked.add(u)
+            cur -= gain[u]
+            old = side[u]
+            side[u] = 1 - old
+            size0 += -1 if old == 0 else 1
+            moves.append(u)
+            for v, wgt in nbrs[u].items():
+                if v in node_set:
+                    gain[v] += (2 * wgt) if side[v] == old else (-2 * wgt)
+            gain[u] = -gain[u]
+            if cur < best_val:
+                best_val, best_prefix = cur, len(moves)
+        for u in moves[best_prefix:]:
+            side[u] = 1 - side[u]
+        if best_val >= best_cut:
+            best_cut = best_val
+            break
+        best_cut = best_val
+    L = {v for v in nodes if side[v] == 0}
+    R = node_set - L
+    return L, R
+
+
+def partition_pairs(st: Structure, rng, imbalance: float = 0.2, leaf_size: int = 8) -> List[Tuple[int, int]]:
+    """Contraction tree by recursive balanced bisection (see above)."""
+    n = st.n_tensors
+    owners: Dict[int, List[int]] = {}
+    for t in range(n):
+        for i in _bits(st.leaf_masks[t]):
+            owners.setdefault(i, []).append(t)
+    nbrs: Dict[int, Dict[int, int]] = {t: {} for t in range(n)}
+    for i, ts in owners.items():
+        for a in ts:
+            for b in ts:
+                if a != b:
+                    nbrs[a][b] = nbrs[a].get(b, 0) + 1
+    masks = list(st.leaf_masks)
+    pairs: List[Tuple[int, int]] = []
+
+    def join(a: int, b: int) -> int:
+        pairs.append((a, b))
+        masks.append(masks[a] ^ masks[b])
+        return n + len(pairs) - 1
+
+    def small(group: List[int]) -> int:
+        # exact order of a small group by subset DP on size(out) cost
+        m = len(group)
+        if m == 1:
+            return group[0]
+        fm = [masks[g] for g in group]
+        sm = [0] * (1 << m)
+        for s in range(1, 1 << m):
+            low = s & -s
+            sm[s] = sm[s ^ low] ^ fm[low.bit_length() - 1]
+        best = [0.0] * (1 << m)
+        split = [0] * (1 << m)
+        for s in range(1, 1 << m):
+            if s & (s - 1) == 0:
+                continue
+            low = s & -s
+            sub = (s - 1) & s
+            b, bs = float("inf"), 0
+            while sub:
+                if sub & low:
+                    y, z = sub, s ^ sub
+                    c = best[y] + best[z] + 2.0 ** bin(sm[y] | sm[z]).count("1")
+                    if c < b:
+                        b, bs = c, y
+                sub = (sub - 1) & s
+            best[s], split[s] = b, bs
+
+        def build(s):
+            if s & (s - 1) == 0:
+                return group[s.bit_length() - 1]
+            y = split[s]
+            return join(build(y), build(s ^ y))
+        return build((1 << m) - 1)
+
+    def rec(group: List[int]) -> int:
+        if len(group) <= leaf_size:
+            return small(group)
+        L, R = _fm_bisect(group, nbrs, rng, imbalance)
+        if not L or not R:
+            half = len(group) // 2
+            L, R = set(group[:half]), set(group[half:])
+        a = rec(sorted(L))
+        b = rec(sorted(R))
+        return join(a, b)
+
+    import sys
+    sys.setrecursionlimit(max(10000, 8 * n))
+    rec(list(range(n)))
+    return pairs
