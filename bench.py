@@ -230,8 +230,23 @@ def main():
     n_batches = -(-run.n_slices // batch)
     roof, per = roofline(run, args.precision, n_batches, run.n_slices - (n_batches - 1) * batch)
     if args.profile_out:
+        from paper_2212_04749_amd import planner as P
+        st = P.Structure.from_network(net, w.open_qubits)
+        smask = sum(1 << i for i in spec.sliced)
+        tree = P.build_tree(st, spec.pairs, smask)
+        prof = run.profile(0, min(batch, run.n_slices))
+        steps = []
+        for j, ((ms, kid, cm, by), dep) in enumerate(zip(prof, run.step_dep())):
+            a, b_ = spec.pairs[j]
+            ma, mb = tree.masks[a], tree.masks[b_]
+            if mb.bit_count() > ma.bit_count():
+                ma, mb = mb, ma
+            k_ = (ma & mb).bit_count()
+            steps.append({"step": j, "ms": ms, "kernel": kid, "cmac": cm, "bytes": by, "dep": dep,
+                          "m": ma.bit_count() - k_, "n": mb.bit_count() - k_, "k": k_,
+                          "w": plan.widths[st.n_tensors + j]})
         with open(args.profile_out, "w") as f:
-            json.dump({"per_kernel": {str(k): v for k, v in per.items()}}, f, indent=1)
+            json.dump({"per_kernel": {str(k): v for k, v in per.items()}, "steps": steps}, f, indent=1)
 
     cpu = None
     if not args.no_cpu_baseline:

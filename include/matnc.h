@@ -109,16 +109,24 @@ int matnc_network_destroy(matnc_network net);
  *   max_rank                cap on every tensor's rank after slicing, <= 32
  *   slice_batch             slices contracted per launch sequence (>= 1);
  *                           the workspace grows with it
+ *   memory_budget           largest workspace (bytes) the plan may need, 0 =
+ *                           no limit.  If the breadth-first plan exceeds it,
+ *                           the distinct bitstrings are split, in reuse-tree
+ *                           (trie) order, into 2, 4, ... chunks that run one
+ *                           after another through the per-batch steps, so
+ *                           that only one chunk's instances are live
+ *                           (MATNC_E_NOMEM if even single keys do not fit)
  * The library derives the reuse structure (distinct projections of the
  * batch onto the outputs below each tree node, gather maps between a node
  * and its children), the storage order of every intermediate, the kernel
  * choice per node and the static memory plan.
- * Errors: MATNC_E_INVALID, MATNC_E_RANK.
+ * Errors: MATNC_E_INVALID, MATNC_E_RANK, MATNC_E_NOMEM.
  */
 int matnc_plan_create(matnc_network net, const int *pairs, int n_sliced,
                       const int *sliced_ids, int n_open, const int *open_qubits,
                       int64_t k, const uint64_t *bitstrings, int precision,
-                      int max_rank, int slice_batch, matnc_plan *out);
+                      int max_rank, int slice_batch, size_t memory_budget,
+                      matnc_plan *out);
 
 typedef struct {
   double cmac_single;       /* S: complex MACs of one amplitude, one slice   */
@@ -133,9 +141,10 @@ typedef struct {
   int max_rank;             /* largest tensor rank after slicing             */
   int n_nodes;              /* contraction steps                             */
   int n_mfma_nodes;         /* steps routed to the MFMA GEMM kernel          */
-  int n_launches_per_batch; /* kernel launches per slice batch               */
+  int n_launches_per_batch; /* kernel launches per slice batch, all chunks   */
   size_t workspace_bytes;   /* device workspace needed by matnc_plan_bind    */
   size_t cache_bytes;       /* part of it holding slice-invariant tensors    */
+  int n_chunks;             /* key chunks the bitstrings are processed in    */
 } matnc_plan_info_t;
 
 int matnc_plan_info(matnc_plan plan, matnc_plan_info_t *info);
@@ -151,7 +160,9 @@ int matnc_plan_set_tensor(matnc_plan plan, int t, const double *data_c128);
  * matnc_plan_bind -- attach the caller's device workspace (at least
  * workspace_bytes, 256-byte aligned) and HIP stream (hipStream_t, may be
  * NULL for the null stream), upload leaf variants, gather maps and offset
- * tables, and capture the per-batch launch sequence as a HIP graph.
+ * tables.  The per-batch launch sequence of each chunk is captured as a HIP
+ * graph on the first execute over a full batch (non-null stream only) and
+ * replayed for every later full batch into the same amplitude buffer.
  * The workspace must stay allocated until the plan is destroyed or re-bound.
  * Errors: MATNC_E_NOMEM, MATNC_E_HIP, MATNC_E_INVALID (misaligned).
  */
@@ -163,7 +174,10 @@ int matnc_plan_bind(matnc_plan plan, void *dev_workspace, size_t bytes, void *hi
  * slice after another in increasing slice id (so any split of a slice range
  * into calls gives bit-identical results).  Slice-invariant intermediates
  * are computed on the first call after bind/set_tensor and kept (stem
- * cache).  Asynchronous on the bound stream.
+ * cache).  With several key chunks, the chunks run one after another: each
+ * first computes its own instances of the invariant nodes wider than one
+ * key (on every call), then runs the slice range.  Asynchronous on the
+ * bound stream.
  * Errors: MATNC_E_STATE (not bound), MATNC_E_INVALID (range), MATNC_E_HIP.
  */
 int matnc_execute(matnc_plan plan, int64_t slice_begin, int64_t slice_end, double *amps_dev);

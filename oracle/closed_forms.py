@@ -11,6 +11,11 @@ theta = pi/2 and zero Deltas (Supplementary Sec. I) acts on |q_a q_b> as
 |00> -> |00>, |01> -> -i |10>, |10> -> -i |01>, |11> -> e^{-i phi} |11>.
 Every such amplitude has modulus 2^(-n/2) when each U_q is one of
 sqrt(X), sqrt(Y), sqrt(W) (all their entries have modulus 1/sqrt(2)).
+
+Slicing (Supplementary Sec. IV.B) fixes a wire of the network to one value;
+on a permutation circuit every wire between gates carries a single basis
+value (the trajectory), so exactly one assignment of a sliced set -- the
+trajectory's -- contributes, and every other slice is exactly zero.
 """
 
 from __future__ import annotations
@@ -58,6 +63,31 @@ def permutation_state(circ: dict):
                 elif a == 1:
                     phase *= complex(math.cos(phi), -math.sin(phi))
     return y, phase
+
+
+def permutation_trajectory(circ: dict):
+    """Basis values along a permutation circuit: entry g lists, for the g-th
+    two-qubit gate in circuit order, ((qubit_a, bit after the gate),
+    (qubit_b, bit after the gate))."""
+    n = int(circ["n_qubits"])
+    body, _ = _last_layer(circ)
+    y = [0] * n
+    out = []
+    for layer in body:
+        if layer["kind"] == "1q":
+            for q, name in layer["gates"]:
+                if name == "X":
+                    y[q] ^= 1
+                elif name != "I":
+                    raise ValueError("closed form: not a permutation circuit")
+        else:
+            for qa, qb, theta, phi in layer["gates"]:
+                if abs(math.cos(theta)) > 1e-12 or math.sin(theta) < 0:
+                    raise ValueError("closed form: fSim must have theta = pi/2")
+                if y[qa] != y[qb]:
+                    y[qa], y[qb] = y[qb], y[qa]
+                out.append(((int(qa), y[qa]), (int(qb), y[qb])))
+    return out
 
 
 def permutation_amplitudes(circ: dict, words) -> np.ndarray:

@@ -52,7 +52,9 @@ class Contraction:
     """One network + plan bound to a torch workspace and stream."""
 
     def __init__(self, net: TensorNetwork, spec: PlanSpec, words, precision: str = "c64",
-                 slice_batch: int = 1, stream=None, device: str = "cuda"):
+                 slice_batch: int = 1, stream=None, device: str = "cuda", memory_budget: Optional[int] = None):
+        """memory_budget: largest workspace in bytes (None: 90% of the device
+        memory free now); above it the bitstrings are processed in chunks."""
         import torch
 
         self.torch = torch
@@ -60,16 +62,20 @@ class Contraction:
         self.spec = spec
         self.words = np.ascontiguousarray(np.asarray(words, dtype=np.uint64))
         self.precision = precision
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
+        if memory_budget is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            memory_budget = int(0.9 * free)
         ranks, ids, data = network_arrays(net)
         self._net = B.matnc_network_create(ranks, ids, data, net.n_qubits, net.output_index)
         self._plan = None
         try:
             self._plan = B.matnc_plan_create(self._net, spec.pairs, spec.sliced, list(spec.open_qubits),
-                                             self.words, PRECISIONS[precision], spec.cap, slice_batch)
+                                             self.words, PRECISIONS[precision], spec.cap, slice_batch,
+                                             memory_budget)
             self.info = B.matnc_plan_info(self._plan)
-            self.device = torch.device(device)
-            if self.device.index is None:
-                self.device = torch.device(self.device.type, torch.cuda.current_device())
             self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
             # allocate on the plan's stream so that the caching allocator
             # orders reuse of this memory after the plan's kernels
@@ -89,13 +95,14 @@ class Contraction:
     @classmethod
     def from_circuit(cls, circ: dict, words, open_qubits: Sequence[int] = (), cap: Optional[int] = None,
                      precision: str = "c64", slice_batch: int = 1, seed: int = 0, trials: int = 32,
-                     exact_slices: Optional[int] = None, stream=None, device: str = "cuda"):
+                     exact_slices: Optional[int] = None, stream=None, device: str = "cuda",
+                     memory_budget: Optional[int] = None):
         net = build_network(circ)
         plan = planner.find_plan(net, words, open_qubits, cap, seed=seed, trials=trials,
                                  exact_slices=exact_slices)
         spec = PlanSpec(plan.pairs, plan.sliced, tuple(sorted(open_qubits)),
                         cap if cap is not None else 32, plan.method)
-        return cls(net, spec, words, precision, slice_batch, stream, device)
+        return cls(net, spec, words, precision, slice_batch, stream, device, memory_budget)
 
     # ------------------------------------------------------------------
     def new_amplitudes(self):

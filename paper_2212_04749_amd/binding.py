@@ -49,6 +49,7 @@ class PlanInfo(ctypes.Structure):
         ("n_launches_per_batch", c_int),
         ("workspace_bytes", c_size_t),
         ("cache_bytes", c_size_t),
+        ("n_chunks", c_int),
     ]
 
     def as_dict(self) -> dict:
@@ -83,7 +84,7 @@ def lib():
                                        POINTER(c_int), POINTER(c_void_p)]
     L.matnc_network_destroy.argtypes = [c_void_p]
     L.matnc_plan_create.argtypes = [c_void_p, POINTER(c_int), c_int, POINTER(c_int), c_int, POINTER(c_int),
-                                    c_int64, POINTER(c_uint64), c_int, c_int, c_int, POINTER(c_void_p)]
+                                    c_int64, POINTER(c_uint64), c_int, c_int, c_int, c_size_t, POINTER(c_void_p)]
     L.matnc_plan_info.argtypes = [c_void_p, POINTER(PlanInfo)]
     L.matnc_plan_set_tensor.argtypes = [c_void_p, c_int, POINTER(c_double)]
     L.matnc_plan_bind.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p]
@@ -158,13 +159,14 @@ def matnc_network_destroy(net: int) -> None:
 
 
 def matnc_plan_create(net: int, pairs, sliced_ids, open_qubits, bitstrings, precision: int, max_rank: int,
-                      slice_batch: int) -> int:
+                      slice_batch: int, memory_budget: int = 0) -> int:
     out = c_void_p()
     flat = [x for p in pairs for x in p]
     words, pwords = u64_array(bitstrings)
     check(lib().matnc_plan_create(c_void_p(net), int_array(flat), len(sliced_ids), int_array(sliced_ids),
                                   len(open_qubits), int_array(open_qubits), len(words), pwords, int(precision),
-                                  int(max_rank), int(slice_batch), ctypes.byref(out)))
+                                  int(max_rank), int(slice_batch), c_size_t(int(memory_budget)),
+                                  ctypes.byref(out)))
     return out.value
 
 

@@ -14,8 +14,10 @@ bool mfma_config_fits(int cfg, int mbits, int nbits, int kbits);
 hipError_t launch_mfma(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st);
 // same kernel, also recording each output instance's maximum (complex-half plans)
 hipError_t launch_mfma_rec(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st);
-hipError_t launch_slice_sum(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t k, int open_bits,
-                            double* amps, hipStream_t st);
+// adds the root instances of slices sigma0 .. sigma0+nb-1 into rows[0..nrows)
+// of amps (root.gmap_off: local root instance of each row position)
+hipError_t launch_slice_sum(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t nrows,
+                            const int32_t* rows, int open_bits, double* amps, hipStream_t st);
 
 // complex-half
 bool chalf_available();
@@ -23,8 +25,8 @@ hipError_t launch_stream_h(const NodeDesc& d, uint64_t ws, const int64_t* sig, h
 int mfma_h_config_count();
 bool mfma_h_config_fits(int cfg, int mbits, int nbits, int kbits);
 hipError_t launch_mfma_h(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st);
-hipError_t launch_slice_sum_h(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t k,
-                              int open_bits, double* amps, hipStream_t st);
+hipError_t launch_slice_sum_h(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t nrows,
+                              const int32_t* rows, int open_bits, double* amps, hipStream_t st);
 
 hipError_t launch_zero(uint64_t ptr, uint64_t bytes, hipStream_t st);
 

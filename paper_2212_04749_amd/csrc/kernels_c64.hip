@@ -184,22 +184,24 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
 // reductions
 
 __global__ __launch_bounds__(256) void k_slice_sum(OpDesc root, uint64_t ws, const int64_t* __restrict__ sig,
-                                                   int nb, int64_t k, int open_bits, double2* __restrict__ amps) {
+                                                   int nb, int64_t nrows, const int32_t* __restrict__ rows,
+                                                   int open_bits, double2* __restrict__ amps) {
   const int32_t* __restrict__ gmap = reinterpret_cast<const int32_t*>(ws + root.gmap_off);
-  const int64_t total = k << open_bits;
+  const int64_t total = nrows << open_bits;
   const int64_t sigma0 = sig[0];
   const int64_t omask = ((int64_t)1 << open_bits) - 1;
   for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < total; g += (int64_t)gridDim.x * 256) {
-    const int64_t i = g >> open_bits;
+    const int64_t rp = g >> open_bits;
     const int64_t o = g & omask;
-    double2 acc = amps[g];
+    const int64_t dst = ((int64_t)rows[rp] << open_bits) + o;
+    double2 acc = amps[dst];
     for (int s = 0; s < nb; ++s) {
-      const int64_t inst = operand_instance(root, gmap, i, s, sigma0 + s);
+      const int64_t inst = operand_instance(root, gmap, rp, s, sigma0 + s);
       const float2 v = reinterpret_cast<const float2*>(ws + root.off + inst * root.inst_bytes)[o];
       acc.x += (double)v.x;
       acc.y += (double)v.y;
     }
-    amps[g] = acc;
+    amps[dst] = acc;
   }
 }
 
@@ -271,12 +273,12 @@ hipError_t launch_mfma_rec(const NodeDesc& d, int cfg, uint64_t ws, const int64_
   return launch_mfma_t<true>(d, cfg, ws, sig, st);
 }
 
-hipError_t launch_slice_sum(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t k, int open_bits,
-                            double* amps, hipStream_t st) {
-  const int64_t total = k << open_bits;
+hipError_t launch_slice_sum(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t nrows,
+                            const int32_t* rows, int open_bits, double* amps, hipStream_t st) {
+  const int64_t total = nrows << open_bits;
   if (total == 0 || nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_slice_sum, dim3(grid_for((total + 255) / 256)), dim3(256), 0, st, root, ws, sig, nb, k,
-                     open_bits, reinterpret_cast<double2*>(amps));
+  hipLaunchKernelGGL(k_slice_sum, dim3(grid_for((total + 255) / 256)), dim3(256), 0, st, root, ws, sig, nb, nrows,
+                     rows, open_bits, reinterpret_cast<double2*>(amps));
   return hipGetLastError();
 }
 

@@ -251,7 +251,9 @@ __global__ __launch_bounds__(256) void k_narrow(NodeDesc d, uint64_t ws, const i
 
 // large K: block = (instance, 256-wide chunk of m) or, for M < 256, one
 // instance with 256 / M groups splitting K
-template <int FL, int NB>
+// KS1: M >= 256, every lane of a block walks the same k, so B's offsets are
+// made wave-uniform and its loads go through the scalar path
+template <int FL, int NB, bool KS1>
 __global__ __launch_bounds__(256) void k_kred(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
   __shared__ uint32_t kofa[256], kofb[256];
   __shared__ float2 part[256 * NB];
@@ -298,7 +300,8 @@ __global__ __launch_bounds__(256) void k_kred(NodeDesc d, uint64_t ws, const int
         for (int u = 0; u < 8; ++u) a[u] = ldop<FL, 1>(pa, ba + kofa[kl + u * KS]);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          const uint32_t ob = bb + kofb[kl + u * KS];
+          uint32_t ob = bb + kofb[kl + u * KS];
+          if constexpr (KS1) ob = __builtin_amdgcn_readfirstlane(ob);
 #pragma unroll
           for (int n = 0; n < NB; ++n) cmac(acc[n], a[u], ldop<FL, 2>(pb, ob + tbn[n]));
         }
@@ -395,12 +398,22 @@ static hipError_t launch_kred(const NodeDesc& d, uint64_t ws, const int64_t* sig
   const int mb = d.mbits < 8 ? d.mbits : 8;
   const int64_t blocks = d.n_inst << (d.mbits - mb);
   const dim3 g(grid_for(blocks)), b(256);
-  switch (d.nbits) {
-    case 0: hipLaunchKernelGGL((k_kred<FL, 1>), g, b, 0, st, d, ws, sig); break;
-    case 1: hipLaunchKernelGGL((k_kred<FL, 2>), g, b, 0, st, d, ws, sig); break;
-    case 2: hipLaunchKernelGGL((k_kred<FL, 4>), g, b, 0, st, d, ws, sig); break;
-    case 3: hipLaunchKernelGGL((k_kred<FL, 8>), g, b, 0, st, d, ws, sig); break;
-    default: return hipErrorInvalidValue;
+  if (d.mbits >= 8) {
+    switch (d.nbits) {
+      case 0: hipLaunchKernelGGL((k_kred<FL, 1, true>), g, b, 0, st, d, ws, sig); break;
+      case 1: hipLaunchKernelGGL((k_kred<FL, 2, true>), g, b, 0, st, d, ws, sig); break;
+      case 2: hipLaunchKernelGGL((k_kred<FL, 4, true>), g, b, 0, st, d, ws, sig); break;
+      case 3: hipLaunchKernelGGL((k_kred<FL, 8, true>), g, b, 0, st, d, ws, sig); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (d.nbits) {
+      case 0: hipLaunchKernelGGL((k_kred<FL, 1, false>), g, b, 0, st, d, ws, sig); break;
+      case 1: hipLaunchKernelGGL((k_kred<FL, 2, false>), g, b, 0, st, d, ws, sig); break;
+      case 2: hipLaunchKernelGGL((k_kred<FL, 4, false>), g, b, 0, st, d, ws, sig); break;
+      case 3: hipLaunchKernelGGL((k_kred<FL, 8, false>), g, b, 0, st, d, ws, sig); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }

@@ -212,8 +212,6 @@ void build_reuse(Plan& P) {
     }
   }
   const PNode& R = P.nodes[P.n_nodes - 1];
-  P.rootmap.resize(P.words.size());
-  for (size_t i = 0; i < P.words.size(); ++i) P.rootmap[i] = find(R.keys, P.words[i] & R.omask);
   P.n_unique = (int64_t)P.nodes[P.n_nodes - 1].keys.size();
   {
     std::vector<uint64_t> u = P.words;
@@ -328,23 +326,120 @@ void fill_table(uint32_t* T, const std::vector<int>& order, const std::vector<in
     }
 }
 
-struct Buf {
+// Chunks of the reuse keys (see plan.h).  Output qubits are ordered by the
+// first tree node that contains them; sorting the distinct root keys by
+// their bits in that order (earliest first, most significant) puts keys
+// that share the early part of the reuse tree next to each other, so a
+// contiguous run of keys needs few distinct instances of the early nodes.
+void build_chunks(Plan& P, int n_chunks) {
+  const int nt = P.net.n_tensors;
+  const int root = P.n_nodes - 1;
+  const PNode& R = P.nodes[root];
+  std::vector<int> first(64, INT_MAX);
+  for (int v = nt; v < P.n_nodes; ++v)
+    for (int q = 0; q < 64; ++q)
+      if ((P.nodes[v].omask >> q) & 1) first[q] = std::min(first[q], v);
+  std::vector<int> perm;
+  for (int q = 0; q < 64; ++q)
+    if ((R.omask >> q) & 1) perm.push_back(q);
+  std::sort(perm.begin(), perm.end(), [&](int a, int b) { return first[a] != first[b] ? first[a] < first[b] : a < b; });
+  auto trie = [&](uint64_t w) {
+    uint64_t k = 0;
+    for (size_t t = 0; t < perm.size(); ++t) k |= ((w >> perm[t]) & 1ull) << (63 - t);
+    return k;
+  };
+  std::vector<uint64_t> rk = R.keys;
+  std::sort(rk.begin(), rk.end(), [&](uint64_t a, uint64_t b) { return trie(a) < trie(b); });
+  const int64_t nr = (int64_t)rk.size();
+  n_chunks = (int)std::max<int64_t>(1, std::min<int64_t>(n_chunks, nr));
+  P.n_chunks = n_chunks;
+  P.chunks.assign(n_chunks, Chunk());
+  auto find = [](const std::vector<uint64_t>& ks, uint64_t u) -> int32_t {
+    return (int32_t)(std::lower_bound(ks.begin(), ks.end(), u) - ks.begin());
+  };
+  for (int c = 0; c < n_chunks; ++c) {
+    Chunk& C = P.chunks[c];
+    const int64_t lo = nr * c / n_chunks, hi = nr * (c + 1) / n_chunks;
+    std::vector<uint64_t> ckeys(rk.begin() + lo, rk.begin() + hi);
+    std::sort(ckeys.begin(), ckeys.end());
+    // local keys of every per-batch node
+    std::vector<std::vector<uint64_t>> local(P.chunked.size());
+    for (size_t i = 0; i < P.chunked.size(); ++i) {
+      const uint64_t m = P.nodes[P.chunked[i]].omask;
+      std::vector<uint64_t>& ks = local[i];
+      for (uint64_t k : ckeys) ks.push_back(k & m);
+      std::sort(ks.begin(), ks.end());
+      ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
+    }
+    C.nodes.assign(P.chunked.size(), ChunkNode());
+    for (size_t i = 0; i < P.chunked.size(); ++i) {
+      const int v = P.chunked[i];
+      const PNode& V = P.nodes[v];
+      ChunkNode& N = C.nodes[i];
+      N.w = (int32_t)local[i].size();
+      const int ca = V.swap ? V.b : V.a;
+      const int cb = V.swap ? V.a : V.b;
+      for (uint64_t u : local[i]) {
+        const int pa = P.chunk_pos[ca], pb = P.chunk_pos[cb];
+        const uint64_t ua = u & P.nodes[ca].omask, ub = u & P.nodes[cb].omask;
+        N.ga.push_back(pa >= 0 ? find(local[pa], ua) : find(P.nodes[ca].keys, ua));
+        N.gb.push_back(pb >= 0 ? find(local[pb], ub) : find(P.nodes[cb].keys, ub));
+      }
+    }
+    // rows of the batch whose root key falls in this chunk
+    const int rp = P.chunk_pos[root];
+    for (size_t i = 0; i < P.words.size(); ++i) {
+      const uint64_t u = P.words[i] & R.omask;
+      if (!std::binary_search(ckeys.begin(), ckeys.end(), u)) continue;
+      C.rows.push_back((int32_t)i);
+      C.rootloc.push_back(rp >= 0 ? find(local[rp], u) : find(R.keys, u));
+    }
+  }
+}
+
+struct ArenaBuf {
   int node;
   uint64_t size;
   int t0, t1;
 };
 
-void build_memory(Plan& P) {
+// schedule, chunks and the static memory plan for a given chunk count
+void build_memory_for(Plan& P, int n_chunks) {
   const int nt = P.net.n_tensors;
   const int root = P.n_nodes - 1;
-  // schedule: invariant internal nodes, then dependent ones, each in SSA order
+  // schedule, each group in SSA order: the slice-invariant nodes computed
+  // once per cache fill (prologue), the slice-invariant nodes computed per
+  // chunk (only with several chunks: those wider than one key), and the
+  // slice-dependent nodes run per slice batch (and chunk)
   P.prologue.clear();
+  P.cpro.clear();
   P.loop.clear();
-  for (int v = nt; v < P.n_nodes; ++v) (P.nodes[v].dep ? P.loop : P.prologue).push_back(v);
+  for (int v = nt; v < P.n_nodes; ++v) {
+    const PNode& V = P.nodes[v];
+    if (V.dep)
+      P.loop.push_back(v);
+    else if (n_chunks > 1 && V.keys.size() > 1)
+      P.cpro.push_back(v);
+    else
+      P.prologue.push_back(v);
+  }
+  P.chunked = P.cpro;
+  P.chunked.insert(P.chunked.end(), P.loop.begin(), P.loop.end());
+  P.chunk_pos.assign(P.n_nodes, -1);
+  for (size_t i = 0; i < P.chunked.size(); ++i) P.chunk_pos[P.chunked[i]] = (int)i;
+  build_chunks(P, n_chunks);
   int t = 0;
   for (int v : P.prologue) P.nodes[v].time = t++;
-  for (int v : P.loop) P.nodes[v].time = t++;
+  for (int v : P.chunked) P.nodes[v].time = t++;
   const int t_end = t + 1;
+  // instance capacity of every node: the largest chunk
+  std::vector<int64_t> cap_inst(P.n_nodes, 0);
+  for (int v = 0; v < P.n_nodes; ++v) cap_inst[v] = (int64_t)P.nodes[v].keys.size();
+  for (size_t i = 0; i < P.chunked.size(); ++i) {
+    int64_t mx = 0;
+    for (const Chunk& C : P.chunks) mx = std::max<int64_t>(mx, C.nodes[i].w);
+    cap_inst[P.chunked[i]] = mx;
+  }
 
   // static region
   uint64_t off = 0;
@@ -354,13 +449,27 @@ void build_memory(Plan& P) {
     PNode& V = P.nodes[v];
     V.tab_off = off;
     off = align_up(off + (uint64_t)TAB_COUNT * kTabSize * 4);
-    V.ga_off = off;
-    off = align_up(off + V.ga.size() * 4);
-    V.gb_off = off;
-    off = align_up(off + V.gb.size() * 4);
+    if (P.chunk_pos[v] < 0) {
+      V.ga_off = off;
+      off = align_up(off + V.ga.size() * 4);
+      V.gb_off = off;
+      off = align_up(off + V.gb.size() * 4);
+    }
   }
-  P.rootmap_off = off;
-  off = align_up(off + P.rootmap.size() * 4);
+  // per-chunk index lists, packed back to back (int32 entries)
+  for (Chunk& C : P.chunks) {
+    for (ChunkNode& N : C.nodes) {
+      N.ga_off = off;
+      off += N.ga.size() * 4;
+      N.gb_off = off;
+      off += N.gb.size() * 4;
+    }
+    C.rows_off = off;
+    off += C.rows.size() * 4;
+    C.rootloc_off = off;
+    off += C.rootloc.size() * 4;
+  }
+  off = align_up(off);
   // leaf variants: keys x 2^nsb instances
   for (int l = 0; l < nt; ++l) {
     PNode& L = P.nodes[l];
@@ -383,10 +492,17 @@ void build_memory(Plan& P) {
     }
     off = align_up(off);
     P.inv_scale_hi = off;
+    P.cpro_scale_lo = off;
+    for (int v : P.cpro) {
+      P.nodes[v].scale_off = off;
+      off += (uint64_t)cap_inst[v] * hs;
+    }
+    off = align_up(off);
+    P.cpro_scale_hi = off;
     P.dep_scale_lo = off;
     for (int v : P.loop) {
       P.nodes[v].scale_off = off;
-      off += (uint64_t)P.nodes[v].keys.size() * P.batch * hs;
+      off += (uint64_t)cap_inst[v] * P.batch * hs;
     }
     off = align_up(off);
     P.dep_scale_hi = off;
@@ -394,29 +510,32 @@ void build_memory(Plan& P) {
   P.static_bytes = off;
 
   // intermediates
-  std::vector<Buf> bufs;
+  std::vector<ArenaBuf> bufs;
   for (int v = nt; v < P.n_nodes; ++v) {
     PNode& V = P.nodes[v];
     V.inst_elems = 1ull << V.idx.size();
-    const uint64_t ninst = (uint64_t)V.keys.size() * (V.dep ? (uint64_t)P.batch : 1ull);
+    const uint64_t ninst = (uint64_t)cap_inst[v] * (V.dep ? (uint64_t)P.batch : 1ull);
     V.buf_bytes = align_up(ninst * V.inst_elems * eb_of(P, v));
+    const PNode& Par = P.nodes[v == root ? root : V.parent];
     int t1;
     if (v == root)
       t1 = t_end;
-    else if (!V.dep && P.nodes[V.parent].dep)
-      t1 = t_end;  // stem cache: kept across all slice batches
+    else if (!V.dep && Par.dep)
+      t1 = t_end;  // cache: read by every slice batch (of its chunk)
+    else if (P.chunk_pos[v] < 0 && P.chunk_pos[V.parent] >= 0)
+      t1 = t_end;  // prologue result read by every chunk
     else
-      t1 = P.nodes[V.parent].time;
+      t1 = Par.time;
     bufs.push_back({v, V.buf_bytes, V.time, t1});
   }
-  std::sort(bufs.begin(), bufs.end(), [](const Buf& x, const Buf& y) {
+  std::sort(bufs.begin(), bufs.end(), [](const ArenaBuf& x, const ArenaBuf& y) {
     return x.size != y.size ? x.size > y.size : x.t0 < y.t0;
   });
   std::vector<std::pair<uint64_t, uint64_t>> placed_range;  // per placed buf
-  std::vector<const Buf*> placed;
+  std::vector<const ArenaBuf*> placed;
   uint64_t arena = 0;
   P.cache_bytes = 0;
-  for (const Buf& b : bufs) {
+  for (const ArenaBuf& b : bufs) {
     std::vector<std::pair<uint64_t, uint64_t>> busy;
     for (size_t i = 0; i < placed.size(); ++i)
       if (!(placed[i]->t1 < b.t0 || b.t1 < placed[i]->t0)) busy.push_back(placed_range[i]);
@@ -433,6 +552,20 @@ void build_memory(Plan& P) {
     if (b.t1 == t_end && b.node != root) P.cache_bytes += b.size;
   }
   P.workspace_bytes = align_up(P.static_bytes + arena);
+}
+
+// smallest power-of-two chunk count whose workspace fits the budget
+void build_memory(Plan& P) {
+  int c = 1;
+  build_memory_for(P, c);
+  const int64_t nr = (int64_t)P.nodes[P.n_nodes - 1].keys.size();
+  while (P.memory_budget && P.workspace_bytes > P.memory_budget && c < nr) {
+    c *= 2;
+    build_memory_for(P, c);
+  }
+  if (P.memory_budget && P.workspace_bytes > P.memory_budget)
+    fail(MATNC_E_NOMEM, "plan needs " + std::to_string(P.workspace_bytes) + " bytes of workspace even with " +
+                            std::to_string(P.n_chunks) + " key chunks; budget " + std::to_string(P.memory_budget));
 }
 
 // writes leaf l's variants (and, for complex-half, its scales) into the
@@ -501,7 +634,8 @@ void fill_leaf_data(Plan& P, int l, unsigned char* dst) {
   }
 }
 
-OpDesc operand_desc(const Plan& P, int child, uint64_t gmap_off) {
+// how a node of chunk c reads child `child` (gmap_off: the gather map)
+OpDesc operand_desc(const Plan& P, int child, uint64_t gmap_off, int c) {
   const PNode& C = P.nodes[child];
   OpDesc o;
   std::memset(&o, 0, sizeof(o));
@@ -510,7 +644,8 @@ OpDesc operand_desc(const Plan& P, int child, uint64_t gmap_off) {
   o.half = C.half_store ? 1 : 0;
   o.gmap_off = gmap_off;
   o.scale_off = C.scale_off;
-  o.w_child = (int32_t)C.keys.size();
+  const int pos = P.chunk_pos.empty() ? -1 : P.chunk_pos[child];
+  o.w_child = pos >= 0 ? P.chunks[c].nodes[pos].w : (int32_t)C.keys.size();
   const bool leaf = child < P.net.n_tensors;
   o.dep = (!leaf && C.dep) ? 1 : 0;
   o.nsb = leaf ? (int32_t)C.sl_bits.size() : 0;
@@ -519,20 +654,23 @@ OpDesc operand_desc(const Plan& P, int child, uint64_t gmap_off) {
   return o;
 }
 
-NodeDesc node_desc(const Plan& P, int v, int nb) {
+NodeDesc node_desc(const Plan& P, int v, int nb, int c = 0) {
   const PNode& V = P.nodes[v];
   NodeDesc d;
   std::memset(&d, 0, sizeof(d));
   const int ca = V.swap ? V.b : V.a;
   const int cb = V.swap ? V.a : V.b;
-  d.A = operand_desc(P, ca, V.ga_off);
-  d.B = operand_desc(P, cb, V.gb_off);
+  const int pos = P.chunk_pos[v];
+  const uint64_t ga = pos >= 0 ? P.chunks[c].nodes[pos].ga_off : V.ga_off;
+  const uint64_t gb = pos >= 0 ? P.chunks[c].nodes[pos].gb_off : V.gb_off;
+  d.A = operand_desc(P, ca, ga, c);
+  d.B = operand_desc(P, cb, gb, c);
   d.c_off = V.off;
   d.c_inst_bytes = V.inst_elems * eb_of(P, v);
   d.c_half = V.half_store ? 1 : 0;
   d.tab_off = V.tab_off;
   d.c_scale_off = V.scale_off;
-  d.w = (int32_t)V.keys.size();
+  d.w = pos >= 0 ? P.chunks[c].nodes[pos].w : (int32_t)V.keys.size();
   d.dep = V.dep ? 1 : 0;
   d.n_inst = (int64_t)d.w * (V.dep ? nb : 1);
   d.mbits = (int32_t)V.M.size();
@@ -541,9 +679,10 @@ NodeDesc node_desc(const Plan& P, int v, int nb) {
   return d;
 }
 
-OpDesc root_desc(const Plan& P) {
+// the root as read by the slice-sum of chunk c: instance per row position
+OpDesc root_desc(const Plan& P, int c) {
   const int root = P.n_nodes - 1;
-  return operand_desc(P, root, P.rootmap_off);
+  return operand_desc(P, root, P.chunks[c].rootloc_off, c);
 }
 
 void launch_node(const Plan& P, const PNode& V, const NodeDesc& d, hipStream_t st) {
@@ -562,10 +701,22 @@ void launch_node(const Plan& P, const PNode& V, const NodeDesc& d, hipStream_t s
   hip_check(e, "kernel launch");
 }
 
-void launch_batch(const Plan& P, int nb, hipStream_t st) {
+// one slice batch of chunk c: the per-batch nodes, then the slice-sum of
+// the chunk's rows into amps (skipped when amps is null)
+void launch_batch(const Plan& P, int c, int nb, hipStream_t st, double* amps) {
+  const int64_t* sig = reinterpret_cast<const int64_t*>(P.ws + P.sigma_off);
+  const int ob = (int)P.open_qubits.size();
   if (P.precision == MATNC_CHALF)
     hip_check(launch_zero(P.ws + P.dep_scale_lo, P.dep_scale_hi - P.dep_scale_lo, st), "clear scales");
-  for (int v : P.loop) launch_node(P, P.nodes[v], node_desc(P, v, nb), st);
+  for (int v : P.loop) launch_node(P, P.nodes[v], node_desc(P, v, nb, c), st);
+  if (!amps) return;
+  const Chunk& C = P.chunks[c];
+  const OpDesc root = root_desc(P, c);
+  const int64_t nrows = (int64_t)C.rows.size();
+  const int32_t* rows = reinterpret_cast<const int32_t*>(P.ws + C.rows_off);
+  hipError_t er = P.precision == MATNC_C64 ? launch_slice_sum(root, P.ws, sig, nb, nrows, rows, ob, amps, st)
+                                           : launch_slice_sum_h(root, P.ws, sig, nb, nrows, rows, ob, amps, st);
+  hip_check(er, "slice sum");
 }
 
 void launch_prologue(const Plan& P, hipStream_t st) {
@@ -574,29 +725,46 @@ void launch_prologue(const Plan& P, hipStream_t st) {
   for (int v : P.prologue) launch_node(P, P.nodes[v], node_desc(P, v, 1), st);
 }
 
-void release_graph(Plan& P) {
-  if (P.graph_exec) (void)hipGraphExecDestroy(P.graph_exec);
-  if (P.graph) (void)hipGraphDestroy(P.graph);
-  P.graph_exec = nullptr;
-  P.graph = nullptr;
+// chunk c's instances of the per-chunk invariant nodes
+void launch_chunk_prologue(const Plan& P, int c, hipStream_t st) {
+  if (P.cpro.empty()) return;
+  if (P.precision == MATNC_CHALF)
+    hip_check(launch_zero(P.ws + P.cpro_scale_lo, P.cpro_scale_hi - P.cpro_scale_lo, st), "clear scales");
+  for (int v : P.cpro) launch_node(P, P.nodes[v], node_desc(P, v, 1, c), st);
 }
 
-// capture one full slice batch as a graph (not possible on the null stream)
-void capture_batch_graph(Plan& P) {
-  release_graph(P);
-  ++P.generation;
-  if (P.stream == nullptr || P.loop.empty()) return;
-  hip_check(hipStreamBeginCapture(P.stream, hipStreamCaptureModeThreadLocal), "begin capture");
-  try {
-    launch_batch(P, P.batch, P.stream);
-  } catch (...) {
-    hipGraph_t g = nullptr;
-    (void)hipStreamEndCapture(P.stream, &g);
+void release_graph(Plan& P) {
+  for (auto g : P.graph_execs)
+    if (g) (void)hipGraphExecDestroy(g);
+  for (auto g : P.graphs)
     if (g) (void)hipGraphDestroy(g);
-    throw;
+  P.graph_execs.clear();
+  P.graphs.clear();
+  P.graph_amps = nullptr;
+}
+
+// capture one full slice batch of every chunk (adding into amps) as graphs;
+// not possible on the null stream
+void capture_batch_graphs(Plan& P, double* amps) {
+  release_graph(P);
+  if (P.stream == nullptr || amps == nullptr) return;
+  for (int c = 0; c < P.n_chunks; ++c) {
+    hip_check(hipStreamBeginCapture(P.stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    hipGraph_t g = nullptr;
+    try {
+      launch_batch(P, c, P.batch, P.stream, amps);
+    } catch (...) {
+      (void)hipStreamEndCapture(P.stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    hip_check(hipStreamEndCapture(P.stream, &g), "end capture");
+    P.graphs.push_back(g);
+    hipGraphExec_t x = nullptr;
+    hip_check(hipGraphInstantiate(&x, g, nullptr, nullptr, 0), "graph instantiate");
+    P.graph_execs.push_back(x);
   }
-  hip_check(hipStreamEndCapture(P.stream, &P.graph), "end capture");
-  hip_check(hipGraphInstantiate(&P.graph_exec, P.graph, nullptr, nullptr, 0), "graph instantiate");
+  P.graph_amps = amps;
 }
 
 // every launch of a complete pass over slices [b, e) into amps (no graphs)
@@ -604,16 +772,13 @@ void launch_pass(Plan& P, int64_t b, int64_t e, double* amps, hipStream_t st) {
   int64_t* sig = reinterpret_cast<int64_t*>(P.ws + P.sigma_off);
   hip_check(launch_set_i64(sig, 0, st), "set sigma");
   launch_prologue(P, st);
-  const OpDesc root = root_desc(P);
-  const int64_t k = (int64_t)P.words.size();
-  const int ob = (int)P.open_qubits.size();
-  for (int64_t s0 = b; s0 < e; s0 += P.batch) {
-    const int nb = (int)std::min<int64_t>(P.batch, e - s0);
-    hip_check(launch_set_i64(sig, s0, st), "set sigma");
-    launch_batch(P, nb, st);
-    hipError_t er = P.precision == MATNC_C64 ? launch_slice_sum(root, P.ws, sig, nb, k, ob, amps, st)
-                                             : launch_slice_sum_h(root, P.ws, sig, nb, k, ob, amps, st);
-    hip_check(er, "slice sum");
+  for (int c = 0; c < P.n_chunks; ++c) {
+    launch_chunk_prologue(P, c, st);
+    for (int64_t s0 = b; s0 < e; s0 += P.batch) {
+      const int nb = (int)std::min<int64_t>(P.batch, e - s0);
+      hip_check(launch_set_i64(sig, s0, st), "set sigma");
+      launch_batch(P, c, nb, st, amps);
+    }
   }
 }
 
@@ -730,7 +895,7 @@ int matnc_network_destroy(matnc_network net) {
 
 int matnc_plan_create(matnc_network net, const int* pairs, int n_sliced, const int* sliced_ids, int n_open,
                       const int* open_qubits, int64_t k, const uint64_t* bitstrings, int precision, int max_rank,
-                      int slice_batch, matnc_plan* out) {
+                      int slice_batch, size_t memory_budget, matnc_plan* out) {
   return guarded([&] {
     if (!net || !out) fail(MATNC_E_INVALID, "null argument");
     const Network& N = net->net;
@@ -753,6 +918,7 @@ int matnc_plan_create(matnc_network net, const int* pairs, int n_sliced, const i
     P.elem_bytes = precision == MATNC_C64 ? 8 : 4;
     P.max_rank_cap = max_rank;
     P.batch = slice_batch;
+    P.memory_budget = memory_budget;
     // tree
     std::vector<char> used(2 * nt - 1, 0);
     for (int j = 0; j < nt - 1; ++j) {
@@ -815,9 +981,10 @@ int matnc_plan_info(matnc_plan plan, matnc_plan_info_t* info) {
     I.max_rank = P.max_rank;
     I.n_nodes = P.net.n_tensors - 1;
     I.n_mfma_nodes = P.n_mfma;
-    I.n_launches_per_batch = (int)P.loop.size() + 2;
+    I.n_launches_per_batch = ((int)P.loop.size() + 2) * P.n_chunks;
     I.workspace_bytes = P.workspace_bytes;
     I.cache_bytes = P.cache_bytes;
+    I.n_chunks = P.n_chunks;
     *info = I;
   });
 }
@@ -874,17 +1041,26 @@ int matnc_plan_bind(matnc_plan plan, void* dev_workspace, size_t bytes, void* hi
       fill_table(T + TAB_CN * kTabSize, V.N, V.idx);
       fill_table(T + TAB_AK * kTabSize, V.K, A.idx);
       fill_table(T + TAB_BK * kTabSize, V.K, B.idx);
-      std::memcpy(P.staging.data() + V.ga_off, V.ga.data(), V.ga.size() * 4);
-      std::memcpy(P.staging.data() + V.gb_off, V.gb.data(), V.gb.size() * 4);
+      if (P.chunk_pos[v] < 0) {
+        std::memcpy(P.staging.data() + V.ga_off, V.ga.data(), V.ga.size() * 4);
+        std::memcpy(P.staging.data() + V.gb_off, V.gb.data(), V.gb.size() * 4);
+      }
     }
-    std::memcpy(P.staging.data() + P.rootmap_off, P.rootmap.data(), P.rootmap.size() * 4);
+    for (const Chunk& C : P.chunks) {
+      for (const ChunkNode& N : C.nodes) {
+        std::memcpy(P.staging.data() + N.ga_off, N.ga.data(), N.ga.size() * 4);
+        std::memcpy(P.staging.data() + N.gb_off, N.gb.data(), N.gb.size() * 4);
+      }
+      std::memcpy(P.staging.data() + C.rows_off, C.rows.data(), C.rows.size() * 4);
+      std::memcpy(P.staging.data() + C.rootloc_off, C.rootloc.data(), C.rootloc.size() * 4);
+    }
     for (int l = 0; l < nt; ++l) fill_leaf_data(P, l, P.staging.data());
     hip_check(hipMemcpyAsync(dev_workspace, P.staging.data(), P.static_bytes, hipMemcpyHostToDevice, P.stream),
               "upload static region");
     hip_check(hipStreamSynchronize(P.stream), "upload static region");
     P.bound = true;
     P.inv_valid = false;
-    capture_batch_graph(P);
+    ++P.generation;
   });
 }
 
@@ -903,20 +1079,22 @@ int matnc_execute(matnc_plan plan, int64_t slice_begin, int64_t slice_end, doubl
       launch_prologue(P, st);
       P.inv_valid = true;
     }
-    const OpDesc root = root_desc(P);
-    const int64_t k = (int64_t)P.words.size();
-    const int ob = (int)P.open_qubits.size();
-    for (int64_t s0 = slice_begin; s0 < slice_end; s0 += P.batch) {
-      const int nb = (int)std::min<int64_t>(P.batch, slice_end - s0);
-      hip_check(launch_set_i64(sig, s0, st), "set sigma");
-      if (nb == P.batch && P.graph_exec)
-        hip_check(hipGraphLaunch(P.graph_exec, st), "graph launch");
-      else
-        launch_batch(P, nb, st);
-      hipError_t e = P.precision == MATNC_C64
-                         ? launch_slice_sum(root, P.ws, sig, nb, k, ob, amps_dev, st)
-                         : launch_slice_sum_h(root, P.ws, sig, nb, k, ob, amps_dev, st);
-      hip_check(e, "slice sum");
+    if (slice_end == slice_begin) return;
+    // full batches replay graphs captured for this amplitude buffer
+    const bool full = slice_end - slice_begin >= P.batch;
+    if (full && st != nullptr && (P.graph_execs.empty() || P.graph_amps != amps_dev))
+      capture_batch_graphs(P, amps_dev);
+    const bool graphs = !P.graph_execs.empty() && P.graph_amps == amps_dev;
+    for (int c = 0; c < P.n_chunks; ++c) {
+      launch_chunk_prologue(P, c, st);
+      for (int64_t s0 = slice_begin; s0 < slice_end; s0 += P.batch) {
+        const int nb = (int)std::min<int64_t>(P.batch, slice_end - s0);
+        hip_check(launch_set_i64(sig, s0, st), "set sigma");
+        if (nb == P.batch && graphs)
+          hip_check(hipGraphLaunch(P.graph_execs[c], st), "graph launch");
+        else
+          launch_batch(P, c, nb, st, amps_dev);
+      }
     }
   });
 }
@@ -960,7 +1138,7 @@ int matnc_plan_autotune(matnc_plan plan, int reps, const char* cache_path) {
       }
     } guard{e0, e1};
     std::vector<int> order(P.prologue);
-    order.insert(order.end(), P.loop.begin(), P.loop.end());
+    order.insert(order.end(), P.chunked.begin(), P.chunked.end());
     for (int v : order) {
       PNode& V = P.nodes[v];
       if (V.kernel != 1) continue;
@@ -1004,7 +1182,8 @@ int matnc_plan_autotune(matnc_plan plan, int reps, const char* cache_path) {
     hip_check(hipStreamSynchronize(st), "autotune sync");
     write_tune_cache(cache_path, cache);
     P.inv_valid = false;
-    capture_batch_graph(P);
+    release_graph(P);
+    ++P.generation;
   });
 }
 
@@ -1026,7 +1205,7 @@ int matnc_plan_profile(matnc_plan plan, int64_t slice_begin, int nb, float* time
     const int nt = P.net.n_tensors;
     const int steps = nt - 1;
     std::vector<int> order(P.prologue);
-    order.insert(order.end(), P.loop.begin(), P.loop.end());
+    order.insert(order.end(), P.chunked.begin(), P.chunked.end());
     std::vector<hipEvent_t> ev(2 * order.size(), nullptr);
     struct EvGuard {
       std::vector<hipEvent_t>& e;
@@ -1040,13 +1219,12 @@ int matnc_plan_profile(matnc_plan plan, int64_t slice_begin, int nb, float* time
     int64_t* sig = reinterpret_cast<int64_t*>(P.ws + P.sigma_off);
     hip_check(launch_set_i64(sig, 0, st), "set sigma");
     if (P.precision == MATNC_CHALF) {
-      hip_check(launch_zero(P.ws + P.inv_scale_lo, P.inv_scale_hi - P.inv_scale_lo, st), "clear scales");
-      hip_check(launch_zero(P.ws + P.dep_scale_lo, P.dep_scale_hi - P.dep_scale_lo, st), "clear scales");
+      hip_check(launch_zero(P.ws + P.inv_scale_lo, P.dep_scale_hi - P.inv_scale_lo, st), "clear scales");
     }
     for (size_t i = 0; i < order.size(); ++i) {
       const int v = order[i];
       const PNode& V = P.nodes[v];
-      if (i == P.prologue.size()) hip_check(launch_set_i64(sig, slice_begin, st), "set sigma");
+      if (i == P.prologue.size() + P.cpro.size()) hip_check(launch_set_i64(sig, slice_begin, st), "set sigma");
       const NodeDesc d = node_desc(P, v, V.dep ? nb : 1);
       hip_check(hipEventRecord(ev[2 * i], st), "event record");
       launch_node(P, V, d, st);
@@ -1068,12 +1246,13 @@ int matnc_plan_profile(matnc_plan plan, int64_t slice_begin, int nb, float* time
       hip_check(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]), "event time");
       time_ms[j] = ms;
       kernel[j] = V.kernel == 1 ? 100 + V.cfg : 0;
-      const double inst = (double)V.keys.size() * (V.dep ? nb : 1);
+      const NodeDesc d = node_desc(P, v, V.dep ? nb : 1);
+      const double inst = (double)d.n_inst;
       cmac[j] = inst * std::ldexp(1.0, (int)(V.M.size() + V.N.size() + V.K.size()));
       const PNode& A = P.nodes[V.swap ? V.b : V.a];
       const PNode& B = P.nodes[V.swap ? V.a : V.b];
-      const double ia = (double)A.keys.size() * (A.dep ? (V.dep ? nb : 1) : 1);
-      const double ib = (double)B.keys.size() * (B.dep ? (V.dep ? nb : 1) : 1);
+      const double ia = (double)d.A.w_child * (d.A.dep ? nb : 1);
+      const double ib = (double)d.B.w_child * (d.B.dep ? nb : 1);
       bytes[j] = (double)eb_of(P, v) * inst * std::ldexp(1.0, (int)V.idx.size()) +
                  (double)eb_of(P, V.swap ? V.b : V.a) * ia * std::ldexp(1.0, (int)A.idx.size()) +
                  (double)eb_of(P, V.swap ? V.a : V.b) * ib * std::ldexp(1.0, (int)B.idx.size());

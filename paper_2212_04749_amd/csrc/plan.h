@@ -61,6 +61,24 @@ struct PNode {
   uint64_t scale_off = 0;        // complex-half: byte offset of the HalfScale array
 };
 
+// One chunk of the reuse keys: the distinct root keys are split, in trie
+// order, into chunks that run one after another.  A chunk first computes its
+// own instances of the slice-invariant nodes wider than one key (its part of
+// the cache), then runs every slice batch through the slice-dependent nodes,
+// so that buffers only ever hold one chunk's instances.
+struct ChunkNode {
+  int32_t w = 0;                      // this chunk's instances of the node
+  std::vector<int32_t> ga, gb;        // gather maps (local or full child indices)
+  uint64_t ga_off = 0, gb_off = 0;
+};
+
+struct Chunk {
+  std::vector<ChunkNode> nodes;       // indexed by position in Plan::chunked
+  std::vector<int32_t> rows;          // input rows whose root key is in the chunk
+  std::vector<int32_t> rootloc;       // local root instance of each of those rows
+  uint64_t rows_off = 0, rootloc_off = 0;
+};
+
 struct Plan {
   Network net;
   int n_nodes = 0;               // n_tensors + steps
@@ -72,16 +90,22 @@ struct Plan {
   int max_rank_cap = 0;
   int batch = 1;
   int elem_bytes = 8;
+  uint64_t memory_budget = 0;    // 0 = no limit
+  int n_chunks = 1;
+  std::vector<Chunk> chunks;
+  std::vector<int> chunk_pos;    // node id -> position in chunked (-1 if not there)
   std::vector<PNode> nodes;
-  std::vector<int32_t> rootmap;
-  uint64_t rootmap_off = 0;
-  uint64_t inv_scale_lo = 0, inv_scale_hi = 0;  // complex-half scale slots of invariant nodes
-  uint64_t dep_scale_lo = 0, dep_scale_hi = 0;  // ... and of per-batch nodes
+  uint64_t inv_scale_lo = 0, inv_scale_hi = 0;    // complex-half scale slots of prologue nodes
+  uint64_t cpro_scale_lo = 0, cpro_scale_hi = 0;  // ... of per-chunk invariant nodes
+  uint64_t dep_scale_lo = 0, dep_scale_hi = 0;    // ... and of per-batch nodes
   uint64_t sigma_off = 0;
   uint64_t static_bytes = 0;
   uint64_t workspace_bytes = 0;
   uint64_t cache_bytes = 0;
-  std::vector<int> prologue, loop;  // node ids in schedule order
+  // node ids in schedule order: computed once per cache fill (prologue),
+  // once per chunk (cpro), per slice batch and chunk (loop); chunked =
+  // cpro followed by loop
+  std::vector<int> prologue, cpro, loop, chunked;
   // costs
   double cmac_single = 0, cmac_multi = 0, cmac_inv = 0, cmac_total = 0;
   double bytes_slice = 0, bytes_inv = 0;
@@ -94,8 +118,9 @@ struct Plan {
   uint64_t ws = 0;
   size_t ws_bytes = 0;
   hipStream_t stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
+  std::vector<hipGraph_t> graphs;          // one full slice batch per chunk
+  std::vector<hipGraphExec_t> graph_execs;
+  double* graph_amps = nullptr;        // amplitude buffer the batch graphs add into
   uint64_t generation = 0;             // bumped whenever launch parameters change
   std::vector<unsigned char> staging;  // host image of the static region
   std::vector<NodeDesc> descs;         // per node (full-batch instance counts)

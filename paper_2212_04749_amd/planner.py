@@ -30,6 +30,16 @@ Slicer: while some tensor is over the cap, slice the index that most
 reduces the total rank overflow above the cap (sum over tensors of
 rank - cap), then the one with the lowest total cost (slice-invariant nodes
 once, the rest times 2^|S|), ties to the lowest index id.
+
+Objective.  ``objective="flops"`` scores plans by the paper's loss: the
+complex MACs over all slices.  ``objective="time"`` (the default) scores
+them by a roofline estimate of the step times on one MI355X: a step moves
+8 * (w(v) 2^|v| + w(a) 2^|a| + w(b) 2^|b|) bytes and does 8 w(v) CMAC(v)
+flops, and takes the longer of bytes / HBM rate and flops / arithmetic rate
+(MFMA for GEMM-shaped steps, vector ALU otherwise), times 2^|S| when it is
+slice-dependent.  Both count the same arithmetic; the time objective also
+sees that wide steps over large tensors are bound by memory traffic, which
+the flop count does not.
 """
 
 from __future__ import annotations
@@ -123,6 +133,23 @@ def widths(tree: Tree, words: np.ndarray) -> List[int]:
     return out
 
 
+# sustained rates of the contraction kernels on one MI355X (complex64)
+RATE_MFMA = 100e12      # flop/s, FP32 MFMA GEMM steps
+RATE_VALU = 40e12       # flop/s, streaming steps
+RATE_HBM = 3.0e12       # byte/s, streaming steps
+LAUNCH_S = 3e-6         # per launch
+
+
+def step_time(w: float, wa: float, wb: float, ra: int, rb: int, rc: int, k: int) -> float:
+    """Estimated seconds of one slice of a pairwise step (see the module
+    docstring); ra >= rb are the operand ranks, k the contracted bits."""
+    m, n = ra - k, rb - k
+    flops = 8.0 * w * 2.0 ** (m + n + k)
+    by = 8.0 * (w * 2.0 ** rc + wa * 2.0 ** ra + wb * 2.0 ** rb)
+    mfma = n + k > 8 and m >= 6 and n >= 5 and k >= 3
+    return max(flops / (RATE_MFMA if mfma else RATE_VALU), by / RATE_HBM) + LAUNCH_S
+
+
 @dataclass
 class Costs:
     S: float            # single-amplitude CMAC per slice
@@ -130,22 +157,33 @@ class Costs:
     total: float        # CMAC over all slices (slice-invariant nodes once)
     max_rank: int
     n_sliced: int
+    time: float = 0.0   # estimated seconds over all slices
+
+    def score(self, objective: str) -> float:
+        return self.time if objective == "time" else self.total
 
 
 def costs(st: Structure, tree: Tree, w: Sequence[int], sliced_mask: int = 0) -> Costs:
     n = st.n_tensors
     dep = [bool(st.leaf_masks[t] & sliced_mask) for t in range(n)]
-    S = Sk = total = 0.0
+    S = Sk = total = tm = 0.0
     nsl = bin(sliced_mask).count("1")
     for j, (a, b) in enumerate(tree.pairs):
         v = n + j
         dep.append(dep[a] or dep[b])
         c = float(2 ** (tree.masks[a] | tree.masks[b]).bit_count())
+        mult = 2.0 ** nsl if dep[v] else 1.0
         S += c
         Sk += w[v] * c
-        total += w[v] * c * (2.0 ** nsl if dep[v] else 1.0)
+        total += w[v] * c * mult
+        ra, rb = tree.masks[a].bit_count(), tree.masks[b].bit_count()
+        wa, wb = w[a], w[b]
+        if rb > ra:
+            ra, rb, wa, wb = rb, ra, wb, wa
+        tm += mult * step_time(w[v], wa, wb, ra, rb, tree.masks[v].bit_count(),
+                               (tree.masks[a] & tree.masks[b]).bit_count())
     mr = max(m.bit_count() for m in tree.masks)
-    return Costs(S, Sk, total, mr, nsl)
+    return Costs(S, Sk, total, mr, nsl, tm)
 
 
 # --------------------------------------------------------------------------
@@ -314,9 +352,50 @@ def stem_branch_pairs(st: Structure, k_eff: int, rng, alpha: float, temp: float,
     return pairs2
 
 
+def timeline_pairs(st: Structure, k_eff: int, rng=None) -> List[Tuple[int, int]]:
+    """Time-ordered trunk: the tensors without closed outputs are absorbed one
+    by one in circuit order (tensor ids follow gate order), as a state is
+    evolved gate by gate; the bright tensors then join by the multi-amplitude
+    step cost, as in the second phase of stem_branch_pairs."""
+    n = st.n_tensors
+    dark = [t for t in range(n) if st.leaf_outputs[t] == 0]
+    pairs: List[Tuple[int, int]] = []
+    masks = list(st.leaf_masks)
+    outs = list(st.leaf_outputs)
+    cur = dark[0] if dark else None
+    for t in dark[1:]:
+        pairs.append((cur, t))
+        masks.append(masks[cur] ^ masks[t])
+        outs.append(0)
+        cur = n + len(pairs) - 1
+    live = ([cur] if cur is not None else []) + [t for t in range(n) if st.leaf_outputs[t] != 0]
+    # absorb bright tensors: at each step the connected pair with the lowest
+    # multi-amplitude cost (exhaustive over live pairs; few bright tensors)
+    live = list(live)
+    while len(live) > 1:
+        best = None
+        for i in range(len(live)):
+            for j in range(i + 1, len(live)):
+                a, b = live[i], live[j]
+                conn = bool(masks[a] & masks[b])
+                o = outs[a] | outs[b]
+                cost = _expected_width(o.bit_count(), k_eff) * 2.0 ** (masks[a] | masks[b]).bit_count()
+                key = (not conn, cost, min(a, b), max(a, b))
+                if best is None or key < best[0]:
+                    best = (key, a, b)
+        _, a, b = best
+        pairs.append((a, b))
+        masks.append(masks[a] ^ masks[b])
+        outs.append(outs[a] | outs[b])
+        live.remove(a)
+        live.remove(b)
+        live.append(n + len(pairs) - 1)
+    return pairs
+
+
 def slice_to_cap(st: Structure, pairs: Sequence[Tuple[int, int]], w: Sequence[int],
                  cap: Optional[int], min_slices: int = 0,
-                 max_sliced: int = 40) -> Tuple[List[int], Costs]:
+                 max_sliced: int = 40, objective: str = "time") -> Tuple[List[int], Costs]:
     """Slicer: while max rank > cap (or fewer than min_slices indices are
     sliced), add the index that most reduces the rank overflow above the
     cap, then minimises the total cost, ties to the lowest id.  Open output
@@ -348,7 +427,7 @@ def slice_to_cap(st: Structure, pairs: Sequence[Tuple[int, int]], w: Sequence[in
             c = costs(st, t2, w, trial_mask)
             # first shrink the total rank overflow above the cap, then cost
             over = 0 if cap is None else sum(max(0, m.bit_count() - cap) for m in t2.masks)
-            key = (over, c.total, i)
+            key = (over, c.score(objective), i)
             if best is None or key < best[0]:
                 best = (key, i)
         if best is None:
@@ -367,27 +446,27 @@ class Plan:
 
 
 def refine(st: Structure, plan: Plan, words: np.ndarray, cap: Optional[int],
-           exact_slices: Optional[int] = None, rounds: int = 4) -> Plan:
+           exact_slices: Optional[int] = None, rounds: int = 4, objective: str = "time") -> Plan:
     """Alternate subtree reconfiguration (sizes 6, 8, 10) with re-slicing
-    until the total cost stops falling."""
+    until the objective stops falling."""
     best = plan
     pairs = list(plan.pairs)
     sliced = list(plan.sliced)
     for _ in range(rounds):
         sl = sum(1 << i for i in sliced)
         for size in (6, 8, 10):
-            pairs = reconfigure(st, pairs, words, cap, sl, size=size, passes=4)
+            pairs = reconfigure(st, pairs, words, cap, sl, size=size, passes=4, objective=objective)
         tree = build_tree(st, pairs)
         w = widths(tree, words)
         c = costs(st, build_tree(st, pairs, sl), w, sl)
         cand = Plan(pairs, sliced, c, w, best.method + "+reconf")
         try:
-            s2, c2 = slice_to_cap(st, pairs, w, cap, min_slices=exact_slices or 0)
-            if (exact_slices is None or len(s2) == exact_slices) and c2.total < c.total:
+            s2, c2 = slice_to_cap(st, pairs, w, cap, min_slices=exact_slices or 0, objective=objective)
+            if (exact_slices is None or len(s2) == exact_slices) and c2.score(objective) < c.score(objective):
                 cand = Plan(pairs, s2, c2, w, best.method + "+reconf")
         except ValueError:
             pass
-        if cand.costs.total < best.costs.total * (1 - 1e-6):
+        if cand.costs.score(objective) < best.costs.score(objective) * (1 - 1e-6):
             best = cand
             pairs, sliced = list(cand.pairs), list(cand.sliced)
         else:
@@ -399,9 +478,13 @@ def find_plan(net: TensorNetwork, words: np.ndarray, open_qubits: Sequence[int] 
               cap: Optional[int] = None, seed: int = 0, trials: int = 64,
               min_slices: int = 0, exact_slices: Optional[int] = None,
               include_greedy: bool = True, refine_top: int = 3, partition_trials: int = 0,
-              rgreedy_trials: int = 0) -> Plan:
+              rgreedy_trials: int = 0, timeline: bool = False, max_sliced: int = 40,
+              objective: str = "time") -> Plan:
     """Search candidate orders; slice each to the cap; refine the cheapest
-    few by subtree reconfiguration; keep the cheapest."""
+    few by subtree reconfiguration; keep the cheapest under ``objective``
+    ("time" or "flops", see the module docstring)."""
+    if objective not in ("time", "flops"):
+        raise ValueError("objective must be 'time' or 'flops'")
     st = Structure.from_network(net, open_qubits)
     words = np.asarray(words, dtype=np.uint64)
     k_eff = int(np.unique(words).size)
@@ -414,6 +497,8 @@ def find_plan(net: TensorNetwork, words: np.ndarray, open_qubits: Sequence[int] 
         temp = float(rng.uniform(0.0, 1.0))
         temp2 = float(rng.uniform(0.0, 0.5)) if t % 2 else 0.0
         candidates.append((f"stem-branch[{t}]", stem_branch_pairs(st, k_eff, rng, alpha, temp, temp2)))
+    if timeline:
+        candidates.append(("timeline", timeline_pairs(st, k_eff)))
     for t in range(rgreedy_trials):
         alpha = float(rng.uniform(0.0, 1.5))
         temp = float(rng.uniform(0.0, 1.0))
@@ -427,22 +512,23 @@ def find_plan(net: TensorNetwork, words: np.ndarray, open_qubits: Sequence[int] 
         tree = build_tree(st, pairs)
         w = widths(tree, words)
         try:
-            sliced, c = slice_to_cap(st, pairs, w, cap, min_slices=(exact_slices or min_slices))
+            sliced, c = slice_to_cap(st, pairs, w, cap, min_slices=(exact_slices or min_slices),
+                                     max_sliced=max_sliced, objective=objective)
         except ValueError:
             continue
         # an exact slice count (C3's 2^8) is preferred; a plan that needs more
         # indices to reach the cap keeps its real count
         miss = 0 if exact_slices is None else abs(len(sliced) - exact_slices)
-        key = (miss, c.total, c.max_rank)
+        key = (miss, c.score(objective), c.max_rank)
         scored.append((key, Plan(list(pairs), sliced, c, w, name)))
     if not scored:
         raise ValueError("no plan meets the cap")
     scored.sort(key=lambda x: x[0])
     out = []
     for key, pl in scored[:max(1, refine_top)]:
-        r = refine(st, pl, words, cap, exact_slices) if refine_top > 0 else pl
+        r = refine(st, pl, words, cap, exact_slices, objective=objective) if refine_top > 0 else pl
         miss = 0 if exact_slices is None else abs(len(r.sliced) - exact_slices)
-        out.append(((miss, r.costs.total, r.costs.max_rank), r))
+        out.append(((miss, r.costs.score(objective), r.costs.max_rank), r))
     out.sort(key=lambda x: x[0])
     return out[0][1]
 
@@ -453,10 +539,10 @@ def find_plan(net: TensorNetwork, words: np.ndarray, open_qubits: Sequence[int] 
 # Take a subtree whose frontier is m <= 8 sub-trees, and replace its internal
 # shape by the cheapest binary tree over that frontier, found by dynamic
 # programming over subsets (3^m work).  The cost of a node is the
-# multi-amplitude step cost w(v) * CMAC(v) (Eq. (1)), multiplied by the
-# number of slices when a sliced index lies below it; a node over the rank
-# cap costs infinity.  Repeating this over all nodes is a local search that
-# never increases the total cost.
+# multi-amplitude step cost w(v) * CMAC(v) (Eq. (1)) or its estimated time,
+# multiplied by the number of slices when a sliced index lies below it; a
+# node over the rank cap costs infinity.  Repeating this over all nodes is a
+# local search that never increases the total cost.
 
 
 class _Tree:
@@ -514,7 +600,19 @@ class _Tree:
         return pairs
 
 
-def _optimal_subtree(T: _Tree, frontier, cap):
+def _node_cost(T: _Tree, objective: str, my: int, mz: int, oy: int, oz: int, w: float) -> float:
+    """Cost of one slice of the step joining operands with index masks my,
+    mz and closed-output masks oy, oz (w: width of the result)."""
+    if objective != "time":
+        return w * 2.0 ** (my | mz).bit_count()
+    ra, rb = my.bit_count(), mz.bit_count()
+    wa, wb = T.width(oy), T.width(oz)
+    if rb > ra:
+        ra, rb, wa, wb = rb, ra, wb, wa
+    return step_time(w, wa, wb, ra, rb, (my ^ mz).bit_count(), (my & mz).bit_count())
+
+
+def _optimal_subtree(T: _Tree, frontier, cap, objective: str = "flops"):
     m = len(frontier)
     full = (1 << m) - 1
     fm = [T.masks[f] for f in frontier]
@@ -542,7 +640,7 @@ def _optimal_subtree(T: _Tree, frontier, cap):
         if cap is not None and bin(mask[s]).count("1") > cap:
             continue
         w = T.width(outs[s])
-        f = w * (mult if dep[s] else 1.0)
+        f = mult if dep[s] else 1.0
         # enumerate splits with the lowest set bit in y to halve the work
         low = s & -s
         sub = (s - 1) & s
@@ -552,7 +650,7 @@ def _optimal_subtree(T: _Tree, frontier, cap):
             if sub & low:
                 y, z = sub, s ^ sub
                 if best[y] < INF and best[z] < INF:
-                    c = best[y] + best[z] + f * 2.0 ** bin(mask[y] | mask[z]).count("1")
+                    c = best[y] + best[z] + f * _node_cost(T, objective, mask[y], mask[z], outs[y], outs[z], w)
                     if c < b:
                         b, bs = c, y
             sub = (sub - 1) & s
@@ -561,17 +659,17 @@ def _optimal_subtree(T: _Tree, frontier, cap):
     return best[full], split
 
 
-def _subtree_cost(T: _Tree, v, frontier_set):
+def _subtree_cost(T: _Tree, v, frontier_set, objective: str = "flops"):
     if v in frontier_set:
         return 0.0
     a, b = T.children[v]
     mult = 2.0 ** T.nsl if T.dep[v] else 1.0
-    c = T.width(T.outs[v]) * mult * 2.0 ** bin(T.masks[a] | T.masks[b]).count("1")
-    return c + _subtree_cost(T, a, frontier_set) + _subtree_cost(T, b, frontier_set)
+    c = mult * _node_cost(T, objective, T.masks[a], T.masks[b], T.outs[a], T.outs[b], T.width(T.outs[v]))
+    return c + _subtree_cost(T, a, frontier_set, objective) + _subtree_cost(T, b, frontier_set, objective)
 
 
 def reconfigure(st: Structure, pairs, words, cap: Optional[int], sliced_mask: int = 0,
-                size: int = 8, passes: int = 2) -> List[Tuple[int, int]]:
+                size: int = 8, passes: int = 2, objective: str = "flops") -> List[Tuple[int, int]]:
     """Local search over subtrees of ``size`` frontier nodes (see above)."""
     words = np.asarray(words, dtype=np.uint64)
     T = _Tree(st, pairs, sliced_mask, words)
@@ -599,8 +697,8 @@ def reconfigure(st: Structure, pairs, words, cap: Optional[int], sliced_mask: in
                 frontier.extend(T.children[f])
             if len(frontier) < 3:
                 continue
-            old = _subtree_cost(T, v, set(frontier))
-            new, split = _optimal_subtree(T, frontier, cap)
+            old = _subtree_cost(T, v, set(frontier), objective)
+            new, split = _optimal_subtree(T, frontier, cap, objective)
             if new < old * (1 - 1e-9):
                 def build(s):
                     if s & (s - 1) == 0:

@@ -152,3 +152,44 @@ def test_c2_full_config_against_stored_oracle():
     n = 30
     assert abs((np.ldexp(np.mean(np.abs(got) ** 2), n) - 1) - (np.ldexp(np.mean(np.abs(ref) ** 2), n) - 1)) <= 1e-4
     run.close()
+
+
+@pytest.mark.parametrize("precision", ["c64", "chalf"])
+def test_key_chunks_match_single_pass(precision):
+    # a memory budget below the breadth-first workspace splits the batch into
+    # trie-ordered key chunks; every instance is computed by the same kernel
+    # on the same operands, so the amplitudes are bit-identical
+    torch = require_gpu()
+    from paper_2212_04749_amd import api, planner
+    from paper_2212_04749_amd.circuit_tn import build_network
+    circ = random_circuit(GridSpec(4, 4), 12, 21)
+    words = uniform_bitstrings(16, 1024, 22)
+    words[5] = words[900]  # a repeated bitstring lands in one chunk's row list twice
+    opens = (3, 9)
+    net = build_network(circ)
+    pl = planner.find_plan(net, words, opens, 14, trials=4)
+    spec = api.PlanSpec(pl.pairs, pl.sliced, opens, 14)
+    say(f"key chunks {precision}")
+    one = api.Contraction(net, spec, words, precision=precision, slice_batch=2)
+    assert one.info.n_chunks == 1
+    budget = int(0.7 * one.info.workspace_bytes)
+    many = api.Contraction(net, spec, words, precision=precision, slice_batch=2, memory_budget=budget)
+    assert many.info.n_chunks >= 2 and many.info.workspace_bytes <= budget
+    a = one.execute()
+    one.synchronize()
+    b = many.execute()
+    many.synchronize()
+    assert torch.equal(a, b)
+    psi = statevector.final_state(circ)
+    full = []
+    for w0 in words:
+        for j in range(4):
+            word = int(w0)
+            for t, q in enumerate(opens):
+                word = (word & ~(1 << q)) | (((j >> t) & 1) << q)
+            full.append(word)
+    ref = statevector.amplitudes_from_state(psi, full)
+    got = b.cpu().numpy()
+    assert rel_err(got[..., 0] + 1j * got[..., 1], ref) <= (3e-3 if precision == "chalf" else 1e-5)
+    one.close()
+    many.close()

@@ -1,0 +1,80 @@
+"""Exact checks at full workload size, where no state vector fits.
+
+On a permutation circuit (X/I single-qubit layers, fSim(pi/2, phi), any
+last layer) every wire between two-qubit gates carries one basis value, so
+of all slices of a sliced network exactly one -- the assignment of the
+trajectory -- contributes, and its partial amplitudes are the full
+amplitudes a(b) = c prod_q U_q[b_q, y_q] (oracle.closed_forms).  Running
+that one slice on the GPU checks the plan, gathers, open legs, groups and
+scaling of the 6x6 depth-14 workload (36 qubits, 8 open legs, 64 groups,
+2^8 slices) against exact values; a neighbouring slice must give zero.
+"""
+
+import numpy as np
+import pytest
+
+from gpu_util import rel_err, require_gpu, say
+from oracle import closed_forms
+from workload import CONFIGS, permutation_circuit
+
+pytestmark = pytest.mark.gpu
+
+
+def trajectory_slice(net, sliced, traj):
+    """Slice id whose bits are the trajectory's values on the sliced wires.
+    Tensor t of the fused network is the t-th two-qubit gate; its first two
+    indices are that gate's output wires (qubit a, qubit b)."""
+    sigma = 0
+    for j, bond in enumerate(sliced):
+        for t, ix in enumerate(net.indices[:len(traj)]):
+            if bond in ix[:2]:
+                (qa, va), (qb, vb) = traj[t]
+                sigma |= (va if bond == ix[0] else vb) << j
+                break
+        else:
+            raise AssertionError("sliced index is not a two-qubit gate output wire")
+    return sigma
+
+
+def expected_block(circ, groups, opens):
+    words = []
+    for g in groups:
+        for j in range(1 << len(opens)):
+            word = int(g)
+            for t, q in enumerate(opens):
+                word |= ((j >> t) & 1) << q
+            words.append(word)
+    a = closed_forms.permutation_amplitudes(circ, np.array(words, dtype=np.uint64))
+    return a.reshape(len(groups), 1 << len(opens))
+
+
+@pytest.mark.parametrize("precision,tol", [("c64", 1e-5), ("chalf", 3e-3)])
+def test_c3_size_permutation_circuit(precision, tol):
+    require_gpu()
+    from paper_2212_04749_amd import api, planner
+    from paper_2212_04749_amd.circuit_tn import build_network
+    w = CONFIGS["C3"]
+    circ = permutation_circuit(w.grid, w.depth, 303)
+    groups = w.bitstrings()
+    opens = w.open_qubits
+    net = build_network(circ)
+    say(f"C3-size permutation {precision}: planning")
+    pl = planner.find_plan(net, groups, opens, w.cap, trials=4, exact_slices=8, refine_top=1)
+    spec = api.PlanSpec(pl.pairs, pl.sliced, tuple(opens), w.cap)
+    run = api.Contraction(net, spec, groups, precision=precision, slice_batch=1)
+    sigma = trajectory_slice(net, pl.sliced, closed_forms.permutation_trajectory(circ))
+    say(f"C3-size permutation {precision}: {run.n_slices} slices, max rank {run.info.max_rank}, slice {sigma}")
+    assert run.n_slices >= 2
+    amps = run.execute(None, sigma, sigma + 1)
+    run.synchronize()
+    a = amps.cpu().numpy()
+    got = a[..., 0] + 1j * a[..., 1]
+    ref = expected_block(circ, groups, opens)
+    assert np.allclose(np.abs(ref), 2.0 ** -18, rtol=1e-12)
+    assert rel_err(got, ref) <= tol
+    other = sigma ^ 1
+    amps2 = run.execute(None, other, other + 1)
+    run.synchronize()
+    a2 = amps2.cpu().numpy()
+    assert np.max(np.abs(a2)) <= 1e-6 * 2.0 ** -18
+    run.close()

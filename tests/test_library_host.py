@@ -147,3 +147,24 @@ def test_contract_pair_batch_counts_complex_elements():
         api.contract_pair(A, Bt[:2], C, pos)      # B holds 2 instances, A 3
     with pytest.raises(ValueError, match="sizes"):
         api.contract_pair(A[:, :-2], Bt, C, pos)  # A not a whole number of instances
+
+
+def test_memory_budget_splits_keys_into_chunks():
+    # a budget below the breadth-first workspace splits the bitstrings into
+    # trie-ordered chunks; a budget no single key fits in is refused
+    circ = random_circuit(GridSpec(4, 4), 12, 21)
+    words = uniform_bitstrings(16, 1024, 22)
+    net, pl, h, p1 = _plan(circ, words, cap=14, batch=2)
+    full = B.matnc_plan_info(p1)
+    assert full.n_chunks == 1
+    budget = int(0.7 * full.workspace_bytes)
+    p2 = B.matnc_plan_create(h, pl.pairs, pl.sliced, [], words, 0, 14, 2, budget)
+    part = B.matnc_plan_info(p2)
+    assert part.n_chunks >= 2 and part.workspace_bytes <= budget
+    assert part.cmac_multi == full.cmac_multi and part.n_unique == full.n_unique
+    with pytest.raises(B.MatncError) as e:
+        B.matnc_plan_create(h, pl.pairs, pl.sliced, [], words, 0, 14, 2, 4096)
+    assert e.value.code == B.MATNC_E_NOMEM
+    for p in (p1, p2):
+        B.matnc_plan_destroy(p)
+    B.matnc_network_destroy(h)

@@ -201,3 +201,28 @@ def test_planted_dropped_slice_is_caught():
              for a in itertools.product((0, 1), repeat=len(sliced.sliced))]
     assert abs(sum(parts) - full) < 1e-13
     assert abs(sum(parts[:-1]) - full) > 1e-8
+
+
+def test_permutation_trajectory_selects_one_slice():
+    # the oracle TN sliced on every wire after the first two-qubit gate of
+    # each of two qubits: only the trajectory's values contribute
+    circ = permutation_circuit(GridSpec(3, 3), 6, 4)
+    traj = closed_forms.permutation_trajectory(circ)
+    words = uniform_bitstrings(9, 4, 9)
+    ref = closed_forms.permutation_amplitudes(circ, words)
+    net = tn.Network(circ)
+    # the oracle network's tensor of the g-th two-qubit gate holds that
+    # gate's output wires as its first two indices
+    two_q = [ix for ix in net.indices if len(ix) == 4]
+    (qa, va), (qb, vb) = traj[0]
+    wires = [two_q[0][0], two_q[0][1]]
+    plan = tn.Plan(circ, sliced=wires)
+    for i, w0 in enumerate(words):
+        bits = np.array([(int(w0) >> q) & 1 for q in range(9)])
+        for x in range(2):
+            for y in range(2):
+                part = plan.slice_partial(bits, [x, y])[0]
+                if (x, y) == (va, vb):
+                    assert abs(part - ref[i]) < 1e-14
+                else:
+                    assert abs(part) < 1e-15
