@@ -122,7 +122,8 @@ def roofline(run, precision, n_batches, nb_last):
         r = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     r["frac"] = r["achieved"] / r["peak"]
     r["traffic"] = None
-    r["kernel"] = f"mfma cfg {kid - 100}" if kid >= 100 else "streaming"
+    r["kernel"] = (f"mfma fan-out cfg {kid - 200}" if kid >= 200 else
+                   f"mfma cfg {kid - 100}" if kid >= 100 else "streaming")
     r["launches"] = e["launches"]
     r["mean_launch_ms"] = e["ms"] / e["launches"]
     r["share_of_step"] = e["ms"] / sum(v["ms"] for v in per.values())

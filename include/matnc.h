@@ -145,6 +145,7 @@ typedef struct {
   size_t workspace_bytes;   /* device workspace needed by matnc_plan_bind    */
   size_t cache_bytes;       /* part of it holding slice-invariant tensors    */
   int n_chunks;             /* key chunks the bitstrings are processed in    */
+  int n_fan_nodes;          /* MFMA steps run as fan-out tiles               */
 } matnc_plan_info_t;
 
 int matnc_plan_info(matnc_plan plan, matnc_plan_info_t *info);
@@ -219,6 +220,8 @@ int matnc_plan_reset_cache(matnc_plan plan);
  * n_tensors - 1) it writes
  *   time_ms[j]  elapsed time of that launch (-1 if the node has no work),
  *   kernel[j]   0 = streaming kernel, 100 + c = MFMA tile configuration c,
+ *               200 + c = MFMA configuration c as fan-out tiles (the output
+ *               instances that share an A instance computed as one GEMM),
  *   cmac[j]     algorithmic complex MACs of the launch (w * instances * 2^(m+n+k)),
  *   bytes[j]    algorithmic HBM bytes of the launch (each output instance
  *               written once, each distinct operand instance read once).

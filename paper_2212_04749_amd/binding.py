@@ -50,6 +50,7 @@ class PlanInfo(ctypes.Structure):
         ("workspace_bytes", c_size_t),
         ("cache_bytes", c_size_t),
         ("n_chunks", c_int),
+        ("n_fan_nodes", c_int),
     ]
 
     def as_dict(self) -> dict:

@@ -9,6 +9,10 @@
 //    tiles, with the bit permutation of each operand folded into its tile
 //    loads through the offset tables of desc.h.  M runs along the MFMA
 //    column (lane-contiguous) so output stores are coalesced along m.
+//    Steps with few columns whose A instance is shared by several output
+//    instances (a node of the reuse tree whose operand is gathered for many
+//    keys) run as fan-out tiles: the instances that read one A instance
+//    fill the columns of one tile, so each A tile is loaded once for all.
 //  * k_slice_sum: FP64 accumulation of the root instances into the caller's
 //    amplitudes, slices added one by one in slice-id order.
 //  * k_xeb: deterministic FP64 sum of |a|^2 and the linear XEB estimate.
@@ -29,7 +33,10 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // Tile: TM = 32*RM*WM values of m, TN = 16*RN*WN complex n, TK complex k.
 // REC: also record the output instance's largest |component| (complex-half
 // plans, whose FP32 stem tensors feed FP16 consumers).
-template <int RM, int RN, int WM, int WN, int TK, bool REC>
+// FAN: the tile's TN columns are TN >> nbits slots of 2^nbits columns, one
+// per output instance of a fan-table row (see NodeDesc); the A tile is
+// loaded once for all of them.
+template <int RM, int RN, int WM, int WN, int TK, bool REC, bool FAN>
 __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
   constexpr int NT = 64 * WM * WN;
   constexpr int TM = 32 * RM * WM;
@@ -37,6 +44,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
   constexpr int EA = TK * TM / NT;
   constexpr int EB = TK * TN / NT;
   static_assert(EA * NT == TK * TM && EB * NT == TK * TN, "tile must split evenly over threads");
+  static_assert(!(REC && FAN), "fan-out tiles do not record maxima");
+  static_assert(!FAN || TN == kFanTileN, "fan-out tiles are kFanTileN columns wide");
   constexpr int APL = TK * TM + 32;        // plane stride (floats), padded
   constexpr int BPL = TK * TN + 16;
   __shared__ float As[2][2 * APL];
@@ -52,18 +61,32 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
   const int wn = wave / WM;
 
   const int64_t mt_count = (int64_t)1 << (d.mbits - __builtin_ctz(TM));
-  const int64_t nt_count = (int64_t)1 << (d.nbits - __builtin_ctz(TN));
+  const int64_t nt_count = FAN ? 1 : (int64_t)1 << (d.nbits - __builtin_ctz(TN));
   const int64_t tiles = mt_count * nt_count;
   const int ksteps = 1 << (d.kbits - __builtin_ctz(TK));
   const int64_t sigma0 = sig[0];
+  // work units: output instances, or (slice, fan row) pairs
+  const int64_t units = FAN ? (d.n_inst / d.w) * d.n_fan : d.n_inst;
+  const int32_t* __restrict__ fan = reinterpret_cast<const int32_t*>(ws + d.fan_off);
+  const uint32_t nmask = (1u << d.nbits) - 1u;
+  const int slots = FAN ? (TN >> d.nbits) : 1;
 
-  for (int64_t blk = blockIdx.x; blk < d.n_inst * tiles; blk += gridDim.x) {
-    const int64_t inst = blk / tiles;
-    const int64_t t = blk - inst * tiles;
+  for (int64_t blk = blockIdx.x; blk < units * tiles; blk += gridDim.x) {
+    const int64_t u = blk / tiles;
+    const int64_t t = blk - u * tiles;
     const uint32_t m0 = (uint32_t)((t % mt_count) * TM);
     const uint32_t n0 = (uint32_t)((t / mt_count) * TN);
-    const int64_t s = d.dep ? inst / d.w : 0;
-    const int64_t j = d.dep ? inst - s * d.w : inst;
+    int64_t s, j;
+    const int32_t* __restrict__ fj = nullptr;
+    if (FAN) {
+      s = d.dep ? u / d.n_fan : 0;
+      fj = fan + (u - s * d.n_fan) * slots;
+      j = fj[0];
+    } else {
+      s = d.dep ? u / d.w : 0;
+      j = d.dep ? u - s * d.w : u;
+    }
+    const int64_t inst = s * d.w + j;  // output instance (slot 0 for fan tiles)
     const int64_t sigma = sigma0 + s;
     const int64_t ai = operand_instance(d.A, glA, j, s, sigma);
     const int64_t bi = operand_instance(d.B, glB, j, s, sigma);
@@ -81,12 +104,22 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
       akk[e] = flat / TM;
       aoff[e] = tlook(tab + TAB_AM * kTabSize, m0 + amm[e]) + tab[TAB_AK * kTabSize + akk[e]];
     }
+    const float2* pbe[EB];  // fan tiles: B instance of each element's slot (null: empty slot)
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const int flat = e * NT + tid;
       bnn[e] = flat % TN;
       bkk[e] = flat / TN;
-      boff[e] = tlook(tab + TAB_BN * kTabSize, n0 + bnn[e]) + tab[TAB_BK * kTabSize + bkk[e]];
+      if (FAN) {
+        const int jg = fj[bnn[e] >> d.nbits];
+        pbe[e] = jg < 0 ? nullptr
+                        : reinterpret_cast<const float2*>(ws + d.B.off +
+                                                          operand_instance(d.B, glB, jg, s, sigma) * d.B.inst_bytes);
+        boff[e] = tlook(tab + TAB_BN * kTabSize, bnn[e] & nmask) + tab[TAB_BK * kTabSize + bkk[e]];
+      } else {
+        pbe[e] = pb;
+        boff[e] = tlook(tab + TAB_BN * kTabSize, n0 + bnn[e]) + tab[TAB_BK * kTabSize + bkk[e]];
+      }
     }
     float2 ra[EA], rb[EB];
     auto gload = [&](int ks) {
@@ -96,7 +129,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
 #pragma unroll
       for (int e = 0; e < EA; ++e) ra[e] = pa[aoff[e] + kba];
 #pragma unroll
-      for (int e = 0; e < EB; ++e) rb[e] = pb[boff[e] + kbb];
+      for (int e = 0; e < EB; ++e) rb[e] = (!FAN || pbe[e]) ? pbe[e][boff[e] + kbb] : make_float2(0.f, 0.f);
     };
     auto lstore = [&](int buf) {
 #pragma unroll
@@ -163,7 +196,15 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
         for (int r = 0; r < 16; r += 2) {
           const int row = 8 * (r >> 2) + 4 * half + (r & 3);
           const uint32_t n = n0 + (wn * RN + q) * 16 + (row >> 1);
-          pc[om + tlook(tab + TAB_CN * kTabSize, n)] = make_float2(acc[i][q][r], acc[i][q][r + 1]);
+          const float2 val = make_float2(acc[i][q][r], acc[i][q][r + 1]);
+          if (FAN) {
+            const int jg = fj[n >> d.nbits];
+            if (jg >= 0)
+              reinterpret_cast<float2*>(ws + d.c_off + (s * d.w + jg) * d.c_inst_bytes)
+                  [om + tlook(tab + TAB_CN * kTabSize, n & nmask)] = val;
+          } else {
+            pc[om + tlook(tab + TAB_CN * kTabSize, n)] = val;
+          }
           if (REC) mx = fmaxf(mx, fmaxf(fabsf(acc[i][q][r]), fabsf(acc[i][q][r + 1])));
         }
       }
@@ -248,29 +289,45 @@ bool mfma_config_fits(int cfg, int mbits, int nbits, int kbits) {
   return mbits >= c.tm_bits && nbits >= c.tn_bits && kbits >= c.tk_bits;
 }
 
-template <bool REC>
+bool mfma_fan_config_fits(int cfg, int mbits, int nbits, int kbits) {
+  if (cfg < 0 || cfg >= mfma_config_count()) return false;
+  const MfmaCfg& c = kMfmaCfgs[cfg];
+  return (1 << c.tn_bits) == kFanTileN && nbits < c.tn_bits && mbits >= c.tm_bits && kbits >= c.tk_bits;
+}
+
+template <bool REC, bool FAN>
 static hipError_t launch_mfma_t(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
   if (d.n_inst == 0) return hipSuccess;
-  if (!mfma_config_fits(cfg, d.mbits, d.nbits, d.kbits)) return hipErrorInvalidValue;
+  const bool fits = FAN ? mfma_fan_config_fits(cfg, d.mbits, d.nbits, d.kbits)
+                        : mfma_config_fits(cfg, d.mbits, d.nbits, d.kbits);
+  if (!fits || (FAN && (d.w <= 0 || d.n_fan <= 0))) return hipErrorInvalidValue;
   const MfmaCfg& c = kMfmaCfgs[cfg];
-  const int64_t tiles = ((int64_t)1 << (d.mbits - c.tm_bits)) * ((int64_t)1 << (d.nbits - c.tn_bits));
-  const unsigned grid = grid_for(d.n_inst * tiles);
+  const int64_t units = FAN ? (d.n_inst / d.w) * d.n_fan : d.n_inst;
+  const int64_t tiles = ((int64_t)1 << (d.mbits - c.tm_bits)) * (FAN ? 1 : ((int64_t)1 << (d.nbits - c.tn_bits)));
+  const unsigned grid = grid_for(units * tiles);
   switch (cfg) {
-    case 0: hipLaunchKernelGGL((k_mfma<2, 1, 2, 2, 8, REC>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 1: hipLaunchKernelGGL((k_mfma<2, 2, 2, 2, 8, REC>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 2: hipLaunchKernelGGL((k_mfma<1, 1, 2, 2, 8, REC>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 3: hipLaunchKernelGGL((k_mfma<4, 1, 2, 2, 8, REC>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 0: hipLaunchKernelGGL((k_mfma<2, 1, 2, 2, 8, REC, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 1:
+      if (FAN) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_mfma<2, 2, 2, 2, 8, REC, false>), dim3(grid), dim3(256), 0, st, d, ws, sig);
+      break;
+    case 2: hipLaunchKernelGGL((k_mfma<1, 1, 2, 2, 8, REC, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 3: hipLaunchKernelGGL((k_mfma<4, 1, 2, 2, 8, REC, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_mfma(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
-  return launch_mfma_t<false>(d, cfg, ws, sig, st);
+  return launch_mfma_t<false, false>(d, cfg, ws, sig, st);
 }
 
 hipError_t launch_mfma_rec(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
-  return launch_mfma_t<true>(d, cfg, ws, sig, st);
+  return launch_mfma_t<true, false>(d, cfg, ws, sig, st);
+}
+
+hipError_t launch_mfma_fan(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
+  return launch_mfma_t<false, true>(d, cfg, ws, sig, st);
 }
 
 hipError_t launch_slice_sum(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t nrows,

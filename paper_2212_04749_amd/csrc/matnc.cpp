@@ -220,6 +220,26 @@ void build_reuse(Plan& P) {
   }
 }
 
+// fan table: the output instances j grouped by the A instance they read
+// (ga[j]), each group cut into rows of `slots` entries (-1 = empty slot)
+void make_fan(const std::vector<int32_t>& ga, int slots, std::vector<int32_t>& out, int64_t& n_fan) {
+  std::vector<int32_t> order(ga.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return ga[x] < ga[y]; });
+  out.clear();
+  n_fan = 0;
+  size_t i = 0;
+  while (i < order.size()) {
+    size_t e = i;
+    while (e < order.size() && ga[order[e]] == ga[order[i]]) ++e;
+    for (size_t c = i; c < e; c += (size_t)slots) {
+      for (int t = 0; t < slots; ++t) out.push_back(c + t < e ? order[c + t] : -1);
+      ++n_fan;
+    }
+    i = e;
+  }
+}
+
 void build_steps(Plan& P) {
   const int nt = P.net.n_tensors;
   P.n_mfma = 0;
@@ -283,6 +303,30 @@ void build_steps(Plan& P) {
           if (mfma_h_config_fits(c, mb, nb, kb)) {
             V.kernel = 1;
             V.cfg = c;
+            break;
+          }
+        }
+      }
+    }
+    // fan-out tiles: few output columns, and the A instance of each output
+    // instance is shared by others (or K is long enough that MFMA on
+    // half-empty tiles still beats the vector units)
+    V.fan = false;
+    V.fanv.clear();
+    V.n_fan = 0;
+    if (V.kernel == 0 && !V.half_store && !V.rec_max && nb < 5 && kb >= 3 && mb >= 6) {
+      std::vector<int32_t> ua(V.ga);
+      std::sort(ua.begin(), ua.end());
+      const double distinct = (double)(std::unique(ua.begin(), ua.end()) - ua.begin());
+      const double reuse = (double)V.ga.size() / std::max(1.0, distinct);
+      if (reuse >= 2.0 || (nb == 4 && kb >= 6)) {
+        const int order[] = {0, 3, 2};
+        for (int c : order) {
+          if (mfma_fan_config_fits(c, mb, nb, kb)) {
+            V.kernel = 1;
+            V.fan = true;
+            V.cfg = c;
+            make_fan(V.ga, kFanTileN >> nb, V.fanv, V.n_fan);
             break;
           }
         }
@@ -385,6 +429,7 @@ void build_chunks(Plan& P, int n_chunks) {
         N.ga.push_back(pa >= 0 ? find(local[pa], ua) : find(P.nodes[ca].keys, ua));
         N.gb.push_back(pb >= 0 ? find(local[pb], ub) : find(P.nodes[cb].keys, ub));
       }
+      if (V.fan) make_fan(N.ga, kFanTileN >> (int)V.N.size(), N.fanv, N.n_fan);
     }
     // rows of the batch whose root key falls in this chunk
     const int rp = P.chunk_pos[root];
@@ -454,6 +499,8 @@ void build_memory_for(Plan& P, int n_chunks) {
       off = align_up(off + V.ga.size() * 4);
       V.gb_off = off;
       off = align_up(off + V.gb.size() * 4);
+      V.fan_off = off;
+      off = align_up(off + V.fanv.size() * 4);
     }
   }
   // per-chunk index lists, packed back to back (int32 entries)
@@ -463,6 +510,8 @@ void build_memory_for(Plan& P, int n_chunks) {
       off += N.ga.size() * 4;
       N.gb_off = off;
       off += N.gb.size() * 4;
+      N.fan_off = off;
+      off += N.fanv.size() * 4;
     }
     C.rows_off = off;
     off += C.rows.size() * 4;
@@ -676,6 +725,10 @@ NodeDesc node_desc(const Plan& P, int v, int nb, int c = 0) {
   d.mbits = (int32_t)V.M.size();
   d.nbits = (int32_t)V.N.size();
   d.kbits = (int32_t)V.K.size();
+  if (V.fan) {
+    d.fan_off = pos >= 0 ? P.chunks[c].nodes[pos].fan_off : V.fan_off;
+    d.n_fan = pos >= 0 ? P.chunks[c].nodes[pos].n_fan : V.n_fan;
+  }
   return d;
 }
 
@@ -688,7 +741,9 @@ OpDesc root_desc(const Plan& P, int c) {
 void launch_node(const Plan& P, const PNode& V, const NodeDesc& d, hipStream_t st) {
   const int64_t* sig = reinterpret_cast<const int64_t*>(P.ws + P.sigma_off);
   hipError_t e;
-  if (P.precision == MATNC_C64) {
+  if (V.fan) {
+    e = launch_mfma_fan(d, V.cfg, P.ws, sig, st);
+  } else if (P.precision == MATNC_C64) {
     e = V.kernel == 1 ? launch_mfma(d, V.cfg, P.ws, sig, st) : launch_stream(d, P.ws, sig, st);
   } else if (V.kernel == 1) {
     e = V.half_store ? launch_mfma_h(d, V.cfg, P.ws, sig, st)
@@ -786,7 +841,7 @@ void launch_pass(Plan& P, int64_t b, int64_t e, double* amps, hipStream_t st) {
 std::string tune_key(const Plan& P, const PNode& V, int64_t n_inst) {
   int lg = 0;
   while ((1LL << lg) < n_inst) ++lg;
-  return std::string(P.precision == MATNC_C64 ? "c64" : "chalf") + (V.half_store ? "/h" : "/f") + "/" +
+  return std::string(P.precision == MATNC_C64 ? "c64" : "chalf") + (V.half_store ? "/h" : V.fan ? "/fan" : "/f") + "/" +
          std::to_string(V.M.size()) + "," + std::to_string(V.N.size()) + "," + std::to_string(V.K.size()) + "/" +
          std::to_string(lg);
 }
@@ -985,6 +1040,8 @@ int matnc_plan_info(matnc_plan plan, matnc_plan_info_t* info) {
     I.workspace_bytes = P.workspace_bytes;
     I.cache_bytes = P.cache_bytes;
     I.n_chunks = P.n_chunks;
+    I.n_fan_nodes = 0;
+    for (int v = P.net.n_tensors; v < P.n_nodes; ++v) I.n_fan_nodes += P.nodes[v].fan ? 1 : 0;
     *info = I;
   });
 }
@@ -1044,12 +1101,14 @@ int matnc_plan_bind(matnc_plan plan, void* dev_workspace, size_t bytes, void* hi
       if (P.chunk_pos[v] < 0) {
         std::memcpy(P.staging.data() + V.ga_off, V.ga.data(), V.ga.size() * 4);
         std::memcpy(P.staging.data() + V.gb_off, V.gb.data(), V.gb.size() * 4);
+        std::memcpy(P.staging.data() + V.fan_off, V.fanv.data(), V.fanv.size() * 4);
       }
     }
     for (const Chunk& C : P.chunks) {
       for (const ChunkNode& N : C.nodes) {
         std::memcpy(P.staging.data() + N.ga_off, N.ga.data(), N.ga.size() * 4);
         std::memcpy(P.staging.data() + N.gb_off, N.gb.data(), N.gb.size() * 4);
+        std::memcpy(P.staging.data() + N.fan_off, N.fanv.data(), N.fanv.size() * 4);
       }
       std::memcpy(P.staging.data() + C.rows_off, C.rows.data(), C.rows.size() * 4);
       std::memcpy(P.staging.data() + C.rootloc_off, C.rootloc.data(), C.rootloc.size() * 4);
@@ -1147,9 +1206,13 @@ int matnc_plan_autotune(matnc_plan plan, int reps, const char* cache_path) {
       auto it = cache.find(key);
       const bool half = V.half_store;
       const int ncfg = half ? mfma_h_config_count() : mfma_config_count();
+      const int mb = (int)V.M.size(), nb = (int)V.N.size(), kb = (int)V.K.size();
+      auto config_fits = [&](int c) {
+        return half ? mfma_h_config_fits(c, mb, nb, kb)
+                    : V.fan ? mfma_fan_config_fits(c, mb, nb, kb) : mfma_config_fits(c, mb, nb, kb);
+      };
       if (it != cache.end()) {
-        const bool fits = half ? mfma_h_config_fits(it->second, (int)V.M.size(), (int)V.N.size(), (int)V.K.size())
-                               : mfma_config_fits(it->second, (int)V.M.size(), (int)V.N.size(), (int)V.K.size());
+        const bool fits = config_fits(it->second);
         if (fits) {
           V.cfg = it->second;
           continue;
@@ -1159,9 +1222,7 @@ int matnc_plan_autotune(matnc_plan plan, int reps, const char* cache_path) {
       int best_cfg = V.cfg;
       bool have = false;
       for (int c = 0; c < ncfg; ++c) {
-        const bool fits = half ? mfma_h_config_fits(c, (int)V.M.size(), (int)V.N.size(), (int)V.K.size())
-                               : mfma_config_fits(c, (int)V.M.size(), (int)V.N.size(), (int)V.K.size());
-        if (!fits) continue;
+        if (!config_fits(c)) continue;
         V.cfg = c;
         launch_node(P, V, d0, st);  // warm-up
         hip_check(hipEventRecord(e0, st), "event record");
@@ -1245,7 +1306,7 @@ int matnc_plan_profile(matnc_plan plan, int64_t slice_begin, int nb, float* time
       float ms = 0.f;
       hip_check(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]), "event time");
       time_ms[j] = ms;
-      kernel[j] = V.kernel == 1 ? 100 + V.cfg : 0;
+      kernel[j] = V.kernel == 1 ? (V.fan ? 200 : 100) + V.cfg : 0;
       const NodeDesc d = node_desc(P, v, V.dep ? nb : 1);
       const double inst = (double)d.n_inst;
       cmac[j] = inst * std::ldexp(1.0, (int)(V.M.size() + V.N.size() + V.K.size()));

@@ -146,8 +146,18 @@ def step_time(w: float, wa: float, wb: float, ra: int, rb: int, rc: int, k: int)
     m, n = ra - k, rb - k
     flops = 8.0 * w * 2.0 ** (m + n + k)
     by = 8.0 * (w * 2.0 ** rc + wa * 2.0 ** ra + wb * 2.0 ** rb)
-    mfma = n + k > 8 and m >= 6 and n >= 5 and k >= 3
-    return max(flops / (RATE_MFMA if mfma else RATE_VALU), by / RATE_HBM) + LAUNCH_S
+    rate = RATE_VALU
+    if n + k > 8 and m >= 6 and n >= 5 and k >= 3:
+        rate = RATE_MFMA
+    elif m >= 6 and k >= 3 and n < 5:
+        # fan-out tiles: output instances sharing an A instance fill the
+        # 32 columns of one MFMA tile; the rate scales with the fill
+        slots = 32 >> n
+        group = w / max(wa, 1.0)
+        if group >= 2.0 or (n == 4 and k >= 6):
+            rows = math.ceil(group / slots)
+            rate = max(RATE_VALU, RATE_MFMA * group / (rows * slots))
+    return max(flops / rate, by / RATE_HBM) + LAUNCH_S
 
 
 @dataclass
@@ -526,7 +536,13 @@ def find_plan(net: TensorNetwork, words: np.ndarray, open_qubits: Sequence[int] 
     scored.sort(key=lambda x: x[0])
     out = []
     for key, pl in scored[:max(1, refine_top)]:
-        r = refine(st, pl, words, cap, exact_slices, objective=objective) if refine_top > 0 else pl
+        r = pl
+        if refine_top > 0:
+            # the flop objective's local search first (it escapes the poor
+            # initial shapes best), then the time objective from there
+            r = refine(st, pl, words, cap, exact_slices, objective="flops")
+            if objective == "time":
+                r = refine(st, r, words, cap, exact_slices, objective="time")
         miss = 0 if exact_slices is None else abs(len(r.sliced) - exact_slices)
         out.append(((miss, r.costs.score(objective), r.costs.max_rank), r))
     out.sort(key=lambda x: x[0])

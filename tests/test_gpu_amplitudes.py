@@ -193,3 +193,28 @@ def test_key_chunks_match_single_pass(precision):
     assert rel_err(got[..., 0] + 1j * got[..., 1], ref) <= (3e-3 if precision == "chalf" else 1e-5)
     one.close()
     many.close()
+
+
+@pytest.mark.parametrize("grid,depth,cap,k,seed,precision", [
+    ((4, 4), 10, 12, 512, 21, "c64"),
+    ((4, 5), 14, None, 1024, 8, "c64"),
+    ((4, 5), 14, None, 1024, 8, "chalf"),
+])
+def test_fan_out_tiles_against_statevector(grid, depth, cap, k, seed, precision):
+    # plans whose gathered steps run as fan-out MFMA tiles (the output
+    # instances sharing an A instance as one GEMM), before and after the
+    # tile autotuner has timed every fitting configuration
+    require_gpu()
+    n = grid[0] * grid[1]
+    circ = random_circuit(GridSpec(*grid), depth, seed)
+    words = uniform_bitstrings(n, k, seed + 1)
+    ref = statevector.amplitudes(circ, words)
+    say(f"fan-out {grid} d{depth} k={k} {precision}")
+    run = contraction(circ, words, cap=cap, batch=2, precision=precision, trials=4)
+    assert run.info.n_fan_nodes >= 1
+    bar = 3e-3 if precision == "chalf" else 1e-5
+    assert rel_err(run.amplitudes(), ref) <= bar
+    run.autotune(reps=1, cache_path="")
+    assert rel_err(run.amplitudes(), ref) <= bar
+    assert abs(run.xeb() - oxeb.linear_xeb(ref, n)) <= 1e-4
+    run.close()
