@@ -49,7 +49,23 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-autotune", action="store_true", help="keep the heuristic MFMA tile choice")
     p.add_argument("--profile-out", default="", help="write the per-step profile as JSON")
+    p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                   help="only run a plain device-to-device copy of MIB MiB five times (calibrates the "
+                        "HBM byte counters of a profiler against a known traffic) and exit")
     return p.parse_args()
+
+
+def copy_probe(mib: int) -> None:
+    """Five launches of torch's copy kernel moving exactly mib MiB in and out."""
+    import torch
+    n = mib << 18  # float32 elements
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 5}))
 
 
 def workload_description(name, w, info, spec):
@@ -97,7 +113,7 @@ def reference_error(name, run, amps_np):
     return {"rel_err": err, "samples": int(len(ref)), "xeb_abs_err_on_samples": abs(xeb_gpu - xeb_ref)}
 
 
-def roofline(run, precision, n_batches, nb_last):
+def roofline(run, precision, n_batches, nb_last, workload):
     """Aggregate a profiled pass per kernel; the dominant kernel's algorithmic
     flops (MFMA) or bytes (streaming) per launch over its mean launch time."""
     prof = run.profile(0, min(run.slice_batch, run.n_slices))
@@ -121,13 +137,34 @@ def roofline(run, precision, n_batches, nb_last):
         achieved = e["bytes"] / t / 1e9
         r = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     r["frac"] = r["achieved"] / r["peak"]
-    r["traffic"] = None
+    r["traffic"] = pmc_traffic(workload, precision, kid)
+    r["algorithmic_bytes_per_launch"] = e["bytes"] / e["launches"]
     r["kernel"] = (f"mfma fan-out cfg {kid - 200}" if kid >= 200 else
                    f"mfma cfg {kid - 100}" if kid >= 100 else "streaming")
     r["launches"] = e["launches"]
     r["mean_launch_ms"] = e["ms"] / e["launches"]
     r["share_of_step"] = e["ms"] / sum(v["ms"] for v in per.values())
     return r, per
+
+
+def pmc_traffic(workload: str, precision: str, kernel_id: int):
+    """HBM bytes per launch of a kernel as measured by rocprofv3 counters
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy-kernel calibration) and
+    recorded in profiles/*.md, or None when no record matches or the kernel
+    sources changed since the counters were taken."""
+    import glob
+    import hashlib
+    import re
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for m in re.finditer(r"<!-- traffic (\{.*?\}) -->", open(path).read()):
+            rec = json.loads(m.group(1))
+            if (rec["workload"], rec["precision"], rec["kernel_id"]) != (workload, precision, kernel_id):
+                continue
+            same = all(os.path.exists(os.path.join(ROOT, f)) and
+                       hashlib.sha256(open(os.path.join(ROOT, f), "rb").read()).hexdigest() == h
+                       for f, h in rec["sources"].items())
+            return float(rec["bytes_per_launch"]) if same else None
+    return None
 
 
 def cpu_baseline(name, w):
@@ -163,6 +200,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU slice sharding is not built",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     import numpy as np
     import torch
     if not torch.cuda.is_available():
@@ -229,7 +269,7 @@ def main():
     xeb = float(xeb_out.cpu().item())
     err = reference_error(name, run, amps_c)
     n_batches = -(-run.n_slices // batch)
-    roof, per = roofline(run, args.precision, n_batches, run.n_slices - (n_batches - 1) * batch)
+    roof, per = roofline(run, args.precision, n_batches, run.n_slices - (n_batches - 1) * batch, name)
     if args.profile_out:
         from paper_2212_04749_amd import planner as P
         st = P.Structure.from_network(net, w.open_qubits)

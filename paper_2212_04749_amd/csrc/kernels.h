@@ -17,6 +17,7 @@ hipError_t launch_mfma_rec(const NodeDesc& d, int cfg, uint64_t ws, const int64_
 // fan-out tiles (d.fan_off / d.n_fan describe the grouping)
 bool mfma_fan_config_fits(int cfg, int mbits, int nbits, int kbits);
 hipError_t launch_mfma_fan(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st);
+hipError_t launch_mfma_fan_rec(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st);
 // adds the root instances of slices sigma0 .. sigma0+nb-1 into rows[0..nrows)
 // of amps (root.gmap_off: local root instance of each row position)
 hipError_t launch_slice_sum(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t nrows,
@@ -28,6 +29,8 @@ hipError_t launch_stream_h(const NodeDesc& d, uint64_t ws, const int64_t* sig, h
 int mfma_h_config_count();
 bool mfma_h_config_fits(int cfg, int mbits, int nbits, int kbits);
 hipError_t launch_mfma_h(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st);
+bool mfma_h_fan_config_fits(int cfg, int mbits, int nbits, int kbits);
+hipError_t launch_mfma_h_fan(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st);
 hipError_t launch_slice_sum_h(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t nrows,
                               const int32_t* rows, int open_bits, double* amps, hipStream_t st);
 

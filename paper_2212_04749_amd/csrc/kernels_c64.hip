@@ -44,8 +44,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
   constexpr int EA = TK * TM / NT;
   constexpr int EB = TK * TN / NT;
   static_assert(EA * NT == TK * TM && EB * NT == TK * TN, "tile must split evenly over threads");
-  static_assert(!(REC && FAN), "fan-out tiles do not record maxima");
   static_assert(!FAN || TN == kFanTileN, "fan-out tiles are kFanTileN columns wide");
+  __shared__ uint32_t s_mx[(REC && FAN) ? TN : 1];  // per-slot maxima (float bits)
   constexpr int APL = TK * TM + 32;        // plane stride (floats), padded
   constexpr int BPL = TK * TN + 16;
   __shared__ float As[2][2 * APL];
@@ -82,6 +82,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
       s = d.dep ? u / d.n_fan : 0;
       fj = fan + (u - s * d.n_fan) * slots;
       j = fj[0];
+      if (REC && tid < slots) s_mx[tid] = 0u;  // ordered before use by the first k-step barrier
     } else {
       s = d.dep ? u / d.w : 0;
       j = d.dep ? u - s * d.w : u;
@@ -198,18 +199,37 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
           const uint32_t n = n0 + (wn * RN + q) * 16 + (row >> 1);
           const float2 val = make_float2(acc[i][q][r], acc[i][q][r + 1]);
           if (FAN) {
-            const int jg = fj[n >> d.nbits];
+            const int g = n >> d.nbits;
+            const int jg = fj[g];  // uniform over the 32 lanes of a half-wave (one n)
             if (jg >= 0)
               reinterpret_cast<float2*>(ws + d.c_off + (s * d.w + jg) * d.c_inst_bytes)
                   [om + tlook(tab + TAB_CN * kTabSize, n & nmask)] = val;
+            if (REC) {
+              // reduce over the half-wave's 32 values of m, one LDS atomic
+              float v = fmaxf(fabsf(val.x), fabsf(val.y));
+#pragma unroll
+              for (int o = 16; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+              if (l32 == 0 && jg >= 0) atomicMax(&s_mx[g], __float_as_uint(v));
+            }
           } else {
             pc[om + tlook(tab + TAB_CN * kTabSize, n)] = val;
+            if (REC) mx = fmaxf(mx, fmaxf(fabsf(acc[i][q][r]), fabsf(acc[i][q][r + 1])));
           }
-          if (REC) mx = fmaxf(mx, fmaxf(fabsf(acc[i][q][r]), fabsf(acc[i][q][r + 1])));
         }
       }
     }
-    if (REC) {
+    if (REC && FAN) {
+      __syncthreads();
+      if (tid < slots) {
+        const int jg = fj[tid];
+        if (jg >= 0) {
+          HalfScale* sc = reinterpret_cast<HalfScale*>(ws + d.c_scale_off) + (s * d.w + jg);
+          sc->e = 0;
+          if (s_mx[tid] > 0u) atomicMax(&sc->mx, s_mx[tid]);
+        }
+      }
+      __syncthreads();  // s_mx is cleared for the next tile
+    } else if (REC) {
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
       if (lane == 0) {
@@ -328,6 +348,10 @@ hipError_t launch_mfma_rec(const NodeDesc& d, int cfg, uint64_t ws, const int64_
 
 hipError_t launch_mfma_fan(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
   return launch_mfma_t<false, true>(d, cfg, ws, sig, st);
+}
+
+hipError_t launch_mfma_fan_rec(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
+  return launch_mfma_t<true, true>(d, cfg, ws, sig, st);
 }
 
 hipError_t launch_slice_sum(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t nrows,

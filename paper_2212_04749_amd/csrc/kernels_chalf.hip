@@ -42,7 +42,10 @@ __device__ __forceinline__ uint32_t ld_h2bits(uint64_t base, uint32_t i, int hal
 }
 
 // TM = 32*RM*WM values of m, TN = 16*RN*WN complex n, TK complex k (multiple of 4)
-template <int RM, int RN, int WM, int WN, int TK>
+// FAN: fan-out tiles as in k_mfma (desc.h): the TN columns are slots of
+// 2^nbits columns, one per output instance sharing the A instance; every
+// slot has its own B scale, output exponent and recorded maximum.
+template <int RM, int RN, int WM, int WN, int TK, bool FAN>
 __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
   constexpr int NT = 64 * WM * WN;
   constexpr int TM = 32 * RM * WM;
@@ -51,8 +54,15 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
   constexpr int EB = TK * TN / NT;
   static_assert(EA * NT == TK * TM && EB * NT == TK * TN, "tile must split evenly over threads");
   static_assert(TK % 4 == 0, "four complex k per instruction");
+  static_assert(!FAN || TN == kFanTileN, "fan-out tiles are kFanTileN columns wide");
   __shared__ uint32_t As[2][TK * TM];  // half2 bits, [k][m]
   __shared__ uint32_t Bs[2][TK * TN];  // half2 bits, [k][n]
+  // fan-out slots: output factor, output exponent, FP32-load factor of B,
+  // recorded maximum (float bits)
+  __shared__ float s_f[FAN ? TN : 1];
+  __shared__ int s_e[FAN ? TN : 1];
+  __shared__ float s_cb[FAN ? TN : 1];
+  __shared__ uint32_t s_mx[FAN ? TN : 1];
 
   const uint32_t* __restrict__ tab = reinterpret_cast<const uint32_t*>(ws + d.tab_off);
   const int32_t* __restrict__ glA = reinterpret_cast<const int32_t*>(ws + d.A.gmap_off);
@@ -63,7 +73,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
   const int wm = wave % WM;
   const int wn = wave / WM;
   const int64_t mt_count = (int64_t)1 << (d.mbits - __builtin_ctz(TM));
-  const int64_t nt_count = (int64_t)1 << (d.nbits - __builtin_ctz(TN));
+  const int64_t nt_count = FAN ? 1 : (int64_t)1 << (d.nbits - __builtin_ctz(TN));
   const int64_t tiles = mt_count * nt_count;
   const int ksteps = 1 << (d.kbits - __builtin_ctz(TK));
   const int64_t sigma0 = sig[0];
@@ -71,14 +81,28 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
   const int l32 = lane & 31;
   const int dsel = l32 & 1;
   const int ncol = l32 >> 1;
+  const int64_t units = FAN ? (d.n_inst / d.w) * d.n_fan : d.n_inst;
+  const int32_t* __restrict__ fan = reinterpret_cast<const int32_t*>(ws + d.fan_off);
+  const uint32_t nmask = (1u << d.nbits) - 1u;
+  const int slots = FAN ? (TN >> d.nbits) : 1;
+  const HalfScale* __restrict__ scB = reinterpret_cast<const HalfScale*>(ws + d.B.scale_off);
 
-  for (int64_t blk = blockIdx.x; blk < d.n_inst * tiles; blk += gridDim.x) {
-    const int64_t inst = blk / tiles;
-    const int64_t t = blk - inst * tiles;
+  for (int64_t blk = blockIdx.x; blk < units * tiles; blk += gridDim.x) {
+    const int64_t u = blk / tiles;
+    const int64_t t = blk - u * tiles;
     const uint32_t m0 = (uint32_t)((t % mt_count) * TM);
     const uint32_t n0 = (uint32_t)((t / mt_count) * TN);
-    const int64_t s = d.dep ? inst / d.w : 0;
-    const int64_t j = d.dep ? inst - s * d.w : inst;
+    int64_t s, j;
+    const int32_t* __restrict__ fj = nullptr;
+    if (FAN) {
+      s = d.dep ? u / d.n_fan : 0;
+      fj = fan + (u - s * d.n_fan) * slots;
+      j = fj[0];
+    } else {
+      s = d.dep ? u / d.w : 0;
+      j = d.dep ? u - s * d.w : u;
+    }
+    const int64_t inst = s * d.w + j;
     const int64_t sigma = sigma0 + s;
     const int64_t ai = operand_instance(d.A, glA, j, s, sigma);
     const int64_t bi = operand_instance(d.B, glB, j, s, sigma);
@@ -107,6 +131,36 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
       mxb *= cb;
     }
     const int ha = d.A.half, hb = d.B.half;
+    if (FAN) {
+      // per-slot scales: B's exponent and load factor, the output exponent
+      if (tid < slots) {
+        const int jg = fj[tid];
+        float f = 0.f, cbg = 1.f;
+        int e = 0;
+        if (jg >= 0) {
+          const HalfScale sg = scB[operand_instance(d.B, glB, jg, s, sigma)];
+          int ebg = sg.e;
+          float mxbg = __uint_as_float(sg.mx);
+          if (!hb && mxbg > 0.f) {
+            int ex;
+            frexpf(mxbg, &ex);
+            ebg = ex - 14;
+            cbg = ldexpf(1.f, -ebg);
+            mxbg *= cbg;
+          }
+          const float bound = ldexpf(mxa * mxbg, d.kbits + 1);
+          int ex = 0;
+          if (bound > 0.f) frexpf(bound, &ex);
+          f = ldexpf(1.f, 15 - ex);
+          e = ea + ebg + ex - 15;
+        }
+        s_f[tid] = f;
+        s_e[tid] = e;
+        s_cb[tid] = cbg;
+        s_mx[tid] = 0u;
+      }
+      __syncthreads();
+    }
 
     uint32_t aoff[EA], boff[EB];
     int akk[EA], bkk[EB], amm[EA], bnn[EB];
@@ -117,12 +171,24 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
       akk[e] = flat / TM;
       aoff[e] = tlook(tab + TAB_AM * kTabSize, m0 + amm[e]) + tab[TAB_AK * kTabSize + akk[e]];
     }
+    uint64_t pbe[EB];  // B instance of each element (fan tiles: its slot's; 0 = empty slot)
+    float cbe[EB];
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const int flat = e * NT + tid;
       bnn[e] = flat % TN;
       bkk[e] = flat / TN;
-      boff[e] = tlook(tab + TAB_BN * kTabSize, n0 + bnn[e]) + tab[TAB_BK * kTabSize + bkk[e]];
+      if (FAN) {
+        const int g = bnn[e] >> d.nbits;
+        const int jg = fj[g];
+        pbe[e] = jg < 0 ? 0 : ws + d.B.off + operand_instance(d.B, glB, jg, s, sigma) * d.B.inst_bytes;
+        cbe[e] = s_cb[g];
+        boff[e] = tlook(tab + TAB_BN * kTabSize, bnn[e] & nmask) + tab[TAB_BK * kTabSize + bkk[e]];
+      } else {
+        pbe[e] = pb;
+        cbe[e] = cb;
+        boff[e] = tlook(tab + TAB_BN * kTabSize, n0 + bnn[e]) + tab[TAB_BK * kTabSize + bkk[e]];
+      }
     }
     uint32_t ra[EA], rb[EB];
     auto gload = [&](int ks) {
@@ -132,7 +198,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
 #pragma unroll
       for (int e = 0; e < EA; ++e) ra[e] = ld_h2bits(pa, aoff[e] + kba, ha, ca);
 #pragma unroll
-      for (int e = 0; e < EB; ++e) rb[e] = ld_h2bits(pb, boff[e] + kbb, hb, cb);
+      for (int e = 0; e < EB; ++e) rb[e] = (!FAN || pbe[e]) ? ld_h2bits(pbe[e], boff[e] + kbb, hb, cbe[e]) : 0u;
     };
     auto lstore = [&](int buf) {
 #pragma unroll
@@ -193,6 +259,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
     int ex = 0;
     if (bound > 0.f) frexpf(bound, &ex);
     const float f = ldexpf(1.f, 15 - ex);
+    const int e_out = ea + eb + ex - 15;
     float mx = 0.f;
 #pragma unroll
     for (int i = 0; i < RM; ++i) {
@@ -204,19 +271,47 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
         for (int r = 0; r < 16; r += 2) {
           const int row = 8 * (r >> 2) + 4 * half + (r & 3);
           const uint32_t n = n0 + (wn * RN + q) * 16 + (row >> 1);
-          const __half2 h = __float22half2_rn(make_float2(acc[i][q][r] * f, acc[i][q][r + 1] * f));
-          pc[om + tlook(tab + TAB_CN * kTabSize, n)] = h;
-          const float2 back = __half22float2(h);
-          mx = fmaxf(mx, fmaxf(fabsf(back.x), fabsf(back.y)));
+          if (FAN) {
+            const int g = n >> d.nbits;
+            const int jg = fj[g];  // uniform over the 32 lanes of a half-wave (one n)
+            const float fg = s_f[g];
+            const __half2 h = __float22half2_rn(make_float2(acc[i][q][r] * fg, acc[i][q][r + 1] * fg));
+            if (jg >= 0)
+              reinterpret_cast<__half2*>(ws + d.c_off + (s * d.w + jg) * d.c_inst_bytes)
+                  [om + tlook(tab + TAB_CN * kTabSize, n & nmask)] = h;
+            const float2 back = __half22float2(h);
+            float v = fmaxf(fabsf(back.x), fabsf(back.y));
+#pragma unroll
+            for (int o2 = 16; o2 > 0; o2 >>= 1) v = fmaxf(v, __shfl_xor(v, o2));
+            if (l32 == 0 && jg >= 0) atomicMax(&s_mx[g], __float_as_uint(v));
+          } else {
+            const __half2 h = __float22half2_rn(make_float2(acc[i][q][r] * f, acc[i][q][r + 1] * f));
+            pc[om + tlook(tab + TAB_CN * kTabSize, n)] = h;
+            const float2 back = __half22float2(h);
+            mx = fmaxf(mx, fmaxf(fabsf(back.x), fabsf(back.y)));
+          }
         }
       }
     }
+    if (FAN) {
+      __syncthreads();
+      if (tid < slots) {
+        const int jg = fj[tid];
+        if (jg >= 0) {
+          HalfScale* sc = reinterpret_cast<HalfScale*>(ws + d.c_scale_off) + (s * d.w + jg);
+          sc->e = s_e[tid];
+          if (s_mx[tid] > 0u) atomicMax(&sc->mx, s_mx[tid]);
+        }
+      }
+      __syncthreads();  // the slot arrays are rewritten by the next tile
+    } else {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-    if (lane == 0) {
-      HalfScale* sc = reinterpret_cast<HalfScale*>(ws + d.c_scale_off) + inst;
-      sc->e = ea + eb + ex - 15;
-      if (mx > 0.f) atomicMax(&sc->mx, __float_as_uint(mx));
+      for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+      if (lane == 0) {
+        HalfScale* sc = reinterpret_cast<HalfScale*>(ws + d.c_scale_off) + inst;
+        sc->e = e_out;
+        if (mx > 0.f) atomicMax(&sc->mx, __float_as_uint(mx));
+      }
     }
   }
 }
@@ -263,6 +358,7 @@ static const MfmaCfgH kMfmaCfgsH[] = {
     {7, 5, 4},  // 1: RM=2 RN=1 WM=2 WN=2, TK=16 -> TM=128, TN=32
     {6, 5, 4},  // 2: RM=1 RN=1 WM=2 WN=2, TK=16 -> TM=64,  TN=32
     {8, 5, 4},  // 3: RM=4 RN=1 WM=2 WN=2, TK=16 -> TM=256, TN=32
+    {7, 5, 3},  // 4: RM=2 RN=1 WM=2 WN=2, TK=8  -> TM=128, TN=32
 };
 
 int mfma_h_config_count() { return (int)(sizeof(kMfmaCfgsH) / sizeof(kMfmaCfgsH[0])); }
@@ -273,20 +369,44 @@ bool mfma_h_config_fits(int cfg, int mbits, int nbits, int kbits) {
   return mbits >= c.tm_bits && nbits >= c.tn_bits && kbits >= c.tk_bits;
 }
 
-hipError_t launch_mfma_h(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
-  if (d.n_inst == 0) return hipSuccess;
-  if (!mfma_h_config_fits(cfg, d.mbits, d.nbits, d.kbits)) return hipErrorInvalidValue;
+bool mfma_h_fan_config_fits(int cfg, int mbits, int nbits, int kbits) {
+  if (cfg < 0 || cfg >= mfma_h_config_count()) return false;
   const MfmaCfgH& c = kMfmaCfgsH[cfg];
-  const int64_t tiles = ((int64_t)1 << (d.mbits - c.tm_bits)) * ((int64_t)1 << (d.nbits - c.tn_bits));
-  const unsigned grid = grid_for(d.n_inst * tiles);
+  return (1 << c.tn_bits) == kFanTileN && nbits < c.tn_bits && mbits >= c.tm_bits && kbits >= c.tk_bits;
+}
+
+template <bool FAN>
+static hipError_t launch_mfma_h_t(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
+  if (d.n_inst == 0) return hipSuccess;
+  const bool fits = FAN ? mfma_h_fan_config_fits(cfg, d.mbits, d.nbits, d.kbits)
+                        : mfma_h_config_fits(cfg, d.mbits, d.nbits, d.kbits);
+  if (!fits || (FAN && (d.w <= 0 || d.n_fan <= 0))) return hipErrorInvalidValue;
+  const MfmaCfgH& c = kMfmaCfgsH[cfg];
+  const int64_t units = FAN ? (d.n_inst / d.w) * d.n_fan : d.n_inst;
+  const int64_t tiles = ((int64_t)1 << (d.mbits - c.tm_bits)) * (FAN ? 1 : ((int64_t)1 << (d.nbits - c.tn_bits)));
+  const unsigned grid = grid_for(units * tiles);
   switch (cfg) {
-    case 0: hipLaunchKernelGGL((k_mfma_h<2, 2, 2, 2, 16>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 1: hipLaunchKernelGGL((k_mfma_h<2, 1, 2, 2, 16>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 2: hipLaunchKernelGGL((k_mfma_h<1, 1, 2, 2, 16>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 3: hipLaunchKernelGGL((k_mfma_h<4, 1, 2, 2, 16>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 0:
+      if (FAN) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_mfma_h<2, 2, 2, 2, 16, false>), dim3(grid), dim3(256), 0, st, d, ws, sig);
+      break;
+    case 1: hipLaunchKernelGGL((k_mfma_h<2, 1, 2, 2, 16, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 2: hipLaunchKernelGGL((k_mfma_h<1, 1, 2, 2, 16, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 3: hipLaunchKernelGGL((k_mfma_h<4, 1, 2, 2, 16, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 4: hipLaunchKernelGGL((k_mfma_h<2, 1, 2, 2, 8, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_mfma_h(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
+  if (!d.c_half) return hipErrorInvalidValue;  // FP16 outputs only
+  return launch_mfma_h_t<false>(d, cfg, ws, sig, st);
+}
+
+hipError_t launch_mfma_h_fan(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
+  if (!d.c_half) return hipErrorInvalidValue;
+  return launch_mfma_h_t<true>(d, cfg, ws, sig, st);
 }
 
 hipError_t launch_slice_sum_h(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t nrows,

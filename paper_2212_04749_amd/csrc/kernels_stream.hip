@@ -346,23 +346,37 @@ __global__ __launch_bounds__(256) void k_generic(NodeDesc d, uint64_t ws, const 
   const int64_t total = d.n_inst << cb;
   const int64_t sigma0 = sig[0];
   const uint64_t kcount = (uint64_t)1 << d.kbits;
-  for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < total; g += (int64_t)gridDim.x * 256) {
-    const int64_t inst = g >> cb;
-    const uint64_t mn = (uint64_t)g & (((uint64_t)1 << cb) - 1);
-    const uint32_t m = (uint32_t)(mn & (((uint64_t)1 << d.mbits) - 1));
-    const uint32_t n = (uint32_t)(mn >> d.mbits);
-    const InstPtrs ip = instance_ptrs(d, ws, inst, sigma0);
-    const uint32_t oa = tlook(tab + TAB_AM * kTabSize, m);
-    const uint32_t ob = tlook(tab + TAB_BN * kTabSize, n);
-    float2 c = make_float2(0.f, 0.f);
-    for (uint64_t k = 0; k < kcount; ++k) {
-      const uint32_t kk = (uint32_t)k;
-      cmac(c, ldop<FL, 1>(ip.pa, oa + tlook(tab + TAB_AK * kTabSize, kk)),
-           ldop<FL, 2>(ip.pb, ob + tlook(tab + TAB_BK * kTabSize, kk)));
+  // lanes of one instance are contiguous: the output maximum is reduced
+  // within segments of a wave before its one atomic
+  const int seg = cb >= 6 ? 64 : (1 << cb);
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < total; base += (int64_t)gridDim.x * 256) {
+    const int64_t g = base + threadIdx.x;
+    const bool live = g < total;
+    float mx = 0.f;
+    OutScale s{1.f, 0};
+    int64_t inst = 0;
+    if (live) {
+      inst = g >> cb;
+      const uint64_t mn = (uint64_t)g & (((uint64_t)1 << cb) - 1);
+      const uint32_t m = (uint32_t)(mn & (((uint64_t)1 << d.mbits) - 1));
+      const uint32_t n = (uint32_t)(mn >> d.mbits);
+      const InstPtrs ip = instance_ptrs(d, ws, inst, sigma0);
+      const uint32_t oa = tlook(tab + TAB_AM * kTabSize, m);
+      const uint32_t ob = tlook(tab + TAB_BN * kTabSize, n);
+      float2 c = make_float2(0.f, 0.f);
+      for (uint64_t k = 0; k < kcount; ++k) {
+        const uint32_t kk = (uint32_t)k;
+        cmac(c, ldop<FL, 1>(ip.pa, oa + tlook(tab + TAB_AK * kTabSize, kk)),
+             ldop<FL, 2>(ip.pb, ob + tlook(tab + TAB_BK * kTabSize, kk)));
+      }
+      s = out_scale<FL>(d, ws, ip.ai, ip.bi);
+      mx = put<FL>(ip.pc, tlook(tab + TAB_CM * kTabSize, m) + tlook(tab + TAB_CN * kTabSize, n), c, s);
     }
-    const OutScale s = out_scale<FL>(d, ws, ip.ai, ip.bi);
-    const float mx = put<FL>(ip.pc, tlook(tab + TAB_CM * kTabSize, m) + tlook(tab + TAB_CN * kTabSize, n), c, s);
-    record_scale<FL>(d, ws, inst, s, mx, true);
+    if constexpr ((FL & kMixBit) != 0) {
+      mx = segment_max(mx, seg);
+      const int lane = threadIdx.x & 63;
+      if (live && (lane & (seg - 1)) == 0) record_scale<FL>(d, ws, inst, s, mx, true);
+    }
   }
 }
 

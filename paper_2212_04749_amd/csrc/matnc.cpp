@@ -258,10 +258,7 @@ void build_steps(Plan& P) {
   }
   for (int v = nt; v < P.n_nodes; ++v) {
     PNode& V = P.nodes[v];
-    V.rec_max = P.precision == MATNC_CHALF && !V.half_store && V.parent >= 0 && P.nodes[V.parent].half_store;
-  }
-  for (int v = nt; v < P.n_nodes; ++v) {
-    PNode& V = P.nodes[v];
+    const bool hm = V.half_store;  // FP16 output: FP16-product MFMA kernels
     const PNode& ca = P.nodes[V.a];
     const PNode& cb = P.nodes[V.b];
     V.swap = cb.idx.size() > ca.idx.size();
@@ -288,7 +285,7 @@ void build_steps(Plan& P) {
     V.cfg = -1;
     if (nb + kb > 8) {
       // MFMA tiles: prefer the widest N tile that fits
-      if (!V.half_store) {
+      if (!hm) {
         const int order[] = {1, 0, 3, 2};
         for (int c : order) {
           if (mfma_config_fits(c, mb, nb, kb)) {
@@ -298,7 +295,7 @@ void build_steps(Plan& P) {
           }
         }
       } else {
-        const int order[] = {0, 1, 3, 2};
+        const int order[] = {0, 1, 3, 2, 4};
         for (int c : order) {
           if (mfma_h_config_fits(c, mb, nb, kb)) {
             V.kernel = 1;
@@ -314,15 +311,17 @@ void build_steps(Plan& P) {
     V.fan = false;
     V.fanv.clear();
     V.n_fan = 0;
-    if (V.kernel == 0 && !V.half_store && !V.rec_max && nb < 5 && kb >= 3 && mb >= 6) {
+    if (V.kernel == 0 && nb < 5 && kb >= 3 && mb >= 6) {
       std::vector<int32_t> ua(V.ga);
       std::sort(ua.begin(), ua.end());
       const double distinct = (double)(std::unique(ua.begin(), ua.end()) - ua.begin());
       const double reuse = (double)V.ga.size() / std::max(1.0, distinct);
       if (reuse >= 2.0 || (nb == 4 && kb >= 6)) {
-        const int order[] = {0, 3, 2};
-        for (int c : order) {
-          if (mfma_fan_config_fits(c, mb, nb, kb)) {
+        const int order_f[] = {0, 3, 2, -1};
+        const int order_h[] = {1, 3, 2, 4};
+        for (int c : hm ? order_h : order_f) {
+          const bool fits = hm ? mfma_h_fan_config_fits(c, mb, nb, kb) : mfma_fan_config_fits(c, mb, nb, kb);
+          if (fits) {
             V.kernel = 1;
             V.fan = true;
             V.cfg = c;
@@ -333,6 +332,7 @@ void build_steps(Plan& P) {
       }
     }
     if (V.kernel == 1) ++P.n_mfma;
+    V.rec_max = false;
     const double cm = std::ldexp(1.0, mb + nb + kb);
     const double w = (double)V.keys.size();
     P.cmac_single += cm;
@@ -348,6 +348,12 @@ void build_steps(Plan& P) {
       P.cmac_total += w * cm;
       P.bytes_inv += by;
     }
+  }
+  // FP32 tensors whose maximum an FP16 consumer needs for its exponent (and
+  // for the scaling of its FP16 products)
+  for (int v = nt; v < P.n_nodes; ++v) {
+    PNode& V = P.nodes[v];
+    V.rec_max = P.precision == MATNC_CHALF && !V.half_store && V.parent >= 0 && P.nodes[V.parent].half_store;
   }
 }
 
@@ -742,7 +748,9 @@ void launch_node(const Plan& P, const PNode& V, const NodeDesc& d, hipStream_t s
   const int64_t* sig = reinterpret_cast<const int64_t*>(P.ws + P.sigma_off);
   hipError_t e;
   if (V.fan) {
-    e = launch_mfma_fan(d, V.cfg, P.ws, sig, st);
+    e = V.half_store ? launch_mfma_h_fan(d, V.cfg, P.ws, sig, st)
+        : V.rec_max  ? launch_mfma_fan_rec(d, V.cfg, P.ws, sig, st)
+                     : launch_mfma_fan(d, V.cfg, P.ws, sig, st);
   } else if (P.precision == MATNC_C64) {
     e = V.kernel == 1 ? launch_mfma(d, V.cfg, P.ws, sig, st) : launch_stream(d, P.ws, sig, st);
   } else if (V.kernel == 1) {
@@ -1204,12 +1212,12 @@ int matnc_plan_autotune(matnc_plan plan, int reps, const char* cache_path) {
       const NodeDesc d0 = node_desc(P, v, V.dep ? P.batch : 1);
       const std::string key = tune_key(P, V, d0.n_inst);
       auto it = cache.find(key);
-      const bool half = V.half_store;
+      const bool half = V.half_store;  // FP16-product MFMA kernels
       const int ncfg = half ? mfma_h_config_count() : mfma_config_count();
       const int mb = (int)V.M.size(), nb = (int)V.N.size(), kb = (int)V.K.size();
       auto config_fits = [&](int c) {
-        return half ? mfma_h_config_fits(c, mb, nb, kb)
-                    : V.fan ? mfma_fan_config_fits(c, mb, nb, kb) : mfma_config_fits(c, mb, nb, kb);
+        if (V.fan) return half ? mfma_h_fan_config_fits(c, mb, nb, kb) : mfma_fan_config_fits(c, mb, nb, kb);
+        return half ? mfma_h_config_fits(c, mb, nb, kb) : mfma_config_fits(c, mb, nb, kb);
       };
       if (it != cache.end()) {
         const bool fits = config_fits(it->second);

@@ -1,0 +1,75 @@
+"""Pins of the multi-amplitude cost figures and of the native oracle.
+
+* Table I of the paper prints, per depth, the flop counts of single- and
+  multi-amplitude contraction and the ideal speedup; the ideal speedup is
+  k * FPOs(single) / FPOs(multi) (k = one million), the quantity the plan
+  reports as k S / S_k (tests/golden/table_speedup.json).
+* S_k brute force: every bitstring's own single-amplitude tree visits each
+  node v with its projection b|O(v); the distinct (v, projection) pairs,
+  each costing CMAC(v), add up to the library's S_k (Eq. (1) with optimal
+  reuse), and S (one bitstring) to its single-amplitude cost.
+* The plain-C state vector equals the numpy one.
+"""
+
+import json
+import os
+
+import numpy as np
+
+from oracle import statevector, sv_native
+from workload import GridSpec, random_circuit, uniform_bitstrings
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def test_ideal_speedup_column_of_table_one():
+    g = json.load(open(os.path.join(HERE, "golden", "table_speedup.json")))
+    for row in g["rows"]:
+        ideal = g["k"] * row["fpos_single"] / row["fpos_multi"]
+        # the table rounds its flop counts to two digits
+        assert abs(ideal - row["ideal_speedup"]) / row["ideal_speedup"] < 0.005
+
+
+def test_multi_amplitude_cost_by_brute_force():
+    from paper_2212_04749_amd import api, binding as B, planner as P
+    from paper_2212_04749_amd.circuit_tn import build_network
+    circ = random_circuit(GridSpec(3, 4), 8, 17)
+    words = uniform_bitstrings(12, 40, 18)
+    net = build_network(circ)
+    pl = P.find_plan(net, words, (), None, trials=2)
+    # brute force over bitstrings: which nodes see which projections
+    n = len(net.indices)
+    out_of = {net.output_index[q]: q for q in range(net.n_qubits)}
+    leaf_idx = [set(ix) for ix in net.indices]
+    below = [{out_of[i] for i in ix if i in out_of} for ix in net.indices]
+    free = [set(i for i in ix if i not in out_of) for ix in net.indices]
+    pairs_seen = set()
+    cmac = {}
+    for j, (a, b) in enumerate(pl.pairs):
+        v = n + j
+        below.append(below[a] | below[b])
+        cmac[v] = 2 ** len(free[a] | free[b])
+        free.append(free[a] ^ free[b])
+    for w in words:
+        for v in range(n, n + len(pl.pairs)):
+            proj = tuple(sorted((q, (int(w) >> q) & 1) for q in below[v]))
+            pairs_seen.add((v, proj))
+    s_k = sum(cmac[v] for v, _ in pairs_seen)
+    s_1 = sum(cmac.values())
+    ranks, ids, data = api.network_arrays(net)
+    h = B.matnc_network_create(ranks, ids, data, net.n_qubits, net.output_index)
+    p = B.matnc_plan_create(h, pl.pairs, [], [], words, 0, 32, 1)
+    info = B.matnc_plan_info(p)
+    assert info.cmac_multi == s_k
+    assert info.cmac_single == s_1
+    assert s_k < len(set(int(x) for x in words)) * s_1  # reuse saves work
+    B.matnc_plan_destroy(p)
+    B.matnc_network_destroy(h)
+
+
+def test_native_statevector_matches_numpy():
+    circ = random_circuit(GridSpec(3, 4), 9, 23)
+    words = uniform_bitstrings(12, 200, 24)
+    a = statevector.amplitudes(circ, words)
+    b = sv_native.amplitudes(circ, words)
+    assert np.max(np.abs(a - b)) < 1e-14
