@@ -1,23 +1,69 @@
 // Device helpers shared by the complex64 and complex-half kernels.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "desc.h"
 
 namespace matnc {
 
-__device__ __forceinline__ uint32_t tlook(const uint32_t* __restrict__ T, uint32_t x) {
+// Workspace addresses are plain integers; a pointer made from one carries no
+// address space, and the compiler then emits FLAT accesses, which also count
+// on the LDS wait counter (every LDS wait would drain the outstanding global
+// loads as well).  Every access to the workspace goes through a global
+// (address space 1) pointer instead.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> gmem(uint64_t a) {
+  return (gptr<T>)a;
+}
+
+// unsigned atomic max on a workspace word (float bits of non-negative values)
+__device__ __forceinline__ void gmax_u32(uint64_t a, uint32_t v) { atomicMax((uint32_t*)a, v); }
+
+// element accessors (HIP's float2 / __half2 classes cannot be copied
+// through an address-space-qualified reference; plain vectors can)
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float2 ldg_f2(uint64_t base, uint64_t i) {
+  const f32x2 v = gmem<const f32x2>(base)[i];
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void stg_f2(uint64_t base, uint64_t i, float2 v) { gmem<f32x2>(base)[i] = f32x2{v.x, v.y}; }
+__device__ __forceinline__ uint32_t ldg_u32(uint64_t base, uint64_t i) { return gmem<const uint32_t>(base)[i]; }
+__device__ __forceinline__ void stg_u32(uint64_t base, uint64_t i, uint32_t v) { gmem<uint32_t>(base)[i] = v; }
+__device__ __forceinline__ HalfScale ldg_scale(uint64_t base, int64_t i) {
+  const u32x2 v = gmem<const u32x2>(base)[i];
+  HalfScale h;
+  h.e = (int32_t)v.x;
+  h.mx = v.y;
+  return h;
+}
+// exponent word of scale slot i, and an atomic max into its maximum word
+__device__ __forceinline__ void stg_scale_e(uint64_t base, int64_t i, int32_t e) {
+  gmem<int32_t>(base + (uint64_t)i * sizeof(HalfScale))[0] = e;
+}
+__device__ __forceinline__ void max_scale_mx(uint64_t base, int64_t i, uint32_t mx_bits) {
+  gmax_u32(base + (uint64_t)i * sizeof(HalfScale) + offsetof(HalfScale, mx), mx_bits);
+}
+
+template <typename P>
+__device__ __forceinline__ uint32_t tlook(P T, uint32_t x) {
   return T[x & 255u] + T[256 + ((x >> 8) & 255u)] + T[512 + ((x >> 16) & 255u)] + T[768 + (x >> 24)];
 }
 
 // offset of coordinate hi * 256 + lo (lo < 256)
-__device__ __forceinline__ uint32_t tlook_split(const uint32_t* __restrict__ T, uint32_t hi, uint32_t lo) {
+template <typename P>
+__device__ __forceinline__ uint32_t tlook_split(P T, uint32_t hi, uint32_t lo) {
   return T[lo] + T[256 + (hi & 255u)] + T[512 + ((hi >> 8) & 255u)] + T[768 + (hi >> 16)];
 }
 
-__device__ __forceinline__ int64_t operand_instance(const OpDesc& o, const int32_t* gmap, int64_t j,
-                                                    int64_t s, int64_t sigma) {
+template <typename P>
+__device__ __forceinline__ int64_t operand_instance(const OpDesc& o, P gmap, int64_t j, int64_t s, int64_t sigma) {
   int64_t v = (int64_t)gmap[j] * o.nsv;
   for (int t = 0; t < o.nsb; ++t) v += ((sigma >> o.sbit[t]) & 1) << t;
   if (o.dep) v += s * (int64_t)o.w_child;

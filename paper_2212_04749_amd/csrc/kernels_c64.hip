@@ -51,9 +51,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
   __shared__ float As[2][2 * APL];
   __shared__ float Bs[2][2 * BPL];
 
-  const uint32_t* __restrict__ tab = reinterpret_cast<const uint32_t*>(ws + d.tab_off);
-  const int32_t* __restrict__ glA = reinterpret_cast<const int32_t*>(ws + d.A.gmap_off);
-  const int32_t* __restrict__ glB = reinterpret_cast<const int32_t*>(ws + d.B.gmap_off);
+  const gptr<const uint32_t> tab = gmem<const uint32_t>(ws + d.tab_off);
+  const gptr<const int32_t> glA = gmem<const int32_t>(ws + d.A.gmap_off);
+  const gptr<const int32_t> glB = gmem<const int32_t>(ws + d.B.gmap_off);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
   const int64_t sigma0 = sig[0];
   // work units: output instances, or (slice, fan row) pairs
   const int64_t units = FAN ? (d.n_inst / d.w) * d.n_fan : d.n_inst;
-  const int32_t* __restrict__ fan = reinterpret_cast<const int32_t*>(ws + d.fan_off);
+  const gptr<const int32_t> fan = gmem<const int32_t>(ws + d.fan_off);
   const uint32_t nmask = (1u << d.nbits) - 1u;
   const int slots = FAN ? (TN >> d.nbits) : 1;
 
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
     const uint32_t m0 = (uint32_t)((t % mt_count) * TM);
     const uint32_t n0 = (uint32_t)((t / mt_count) * TN);
     int64_t s, j;
-    const int32_t* __restrict__ fj = nullptr;
+    gptr<const int32_t> fj = nullptr;
     if (FAN) {
       s = d.dep ? u / d.n_fan : 0;
       fj = fan + (u - s * d.n_fan) * slots;
@@ -91,9 +91,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
     const int64_t sigma = sigma0 + s;
     const int64_t ai = operand_instance(d.A, glA, j, s, sigma);
     const int64_t bi = operand_instance(d.B, glB, j, s, sigma);
-    const float2* __restrict__ pa = reinterpret_cast<const float2*>(ws + d.A.off + ai * d.A.inst_bytes);
-    const float2* __restrict__ pb = reinterpret_cast<const float2*>(ws + d.B.off + bi * d.B.inst_bytes);
-    float2* __restrict__ pc = reinterpret_cast<float2*>(ws + d.c_off + inst * d.c_inst_bytes);
+    const gptr<const f32x2> pa = gmem<const f32x2>(ws + d.A.off + ai * d.A.inst_bytes);
+    const gptr<const f32x2> pb = gmem<const f32x2>(ws + d.B.off + bi * d.B.inst_bytes);
+    const gptr<f32x2> pc = gmem<f32x2>(ws + d.c_off + inst * d.c_inst_bytes);
 
     // per-thread load coordinates (fixed across k steps)
     uint32_t aoff[EA], boff[EB];
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
       akk[e] = flat / TM;
       aoff[e] = tlook(tab + TAB_AM * kTabSize, m0 + amm[e]) + tab[TAB_AK * kTabSize + akk[e]];
     }
-    const float2* pbe[EB];  // fan tiles: B instance of each element's slot (null: empty slot)
+    gptr<const f32x2> pbe[EB];  // fan tiles: B instance of each element's slot (null: empty slot)
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const int flat = e * NT + tid;
@@ -114,15 +114,14 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
       if (FAN) {
         const int jg = fj[bnn[e] >> d.nbits];
         pbe[e] = jg < 0 ? nullptr
-                        : reinterpret_cast<const float2*>(ws + d.B.off +
-                                                          operand_instance(d.B, glB, jg, s, sigma) * d.B.inst_bytes);
+                        : gmem<const f32x2>(ws + d.B.off + operand_instance(d.B, glB, jg, s, sigma) * d.B.inst_bytes);
         boff[e] = tlook(tab + TAB_BN * kTabSize, bnn[e] & nmask) + tab[TAB_BK * kTabSize + bkk[e]];
       } else {
         pbe[e] = pb;
         boff[e] = tlook(tab + TAB_BN * kTabSize, n0 + bnn[e]) + tab[TAB_BK * kTabSize + bkk[e]];
       }
     }
-    float2 ra[EA], rb[EB];
+    f32x2 ra[EA], rb[EB];
     auto gload = [&](int ks) {
       const uint32_t k0 = (uint32_t)ks * TK;
       const uint32_t kba = tlook(tab + TAB_AK * kTabSize, k0);
@@ -130,7 +129,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
 #pragma unroll
       for (int e = 0; e < EA; ++e) ra[e] = pa[aoff[e] + kba];
 #pragma unroll
-      for (int e = 0; e < EB; ++e) rb[e] = (!FAN || pbe[e]) ? pbe[e][boff[e] + kbb] : make_float2(0.f, 0.f);
+      for (int e = 0; e < EB; ++e) rb[e] = (!FAN || pbe[e]) ? pbe[e][boff[e] + kbb] : f32x2{0.f, 0.f};
     };
     auto lstore = [&](int buf) {
 #pragma unroll
@@ -197,12 +196,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
         for (int r = 0; r < 16; r += 2) {
           const int row = 8 * (r >> 2) + 4 * half + (r & 3);
           const uint32_t n = n0 + (wn * RN + q) * 16 + (row >> 1);
-          const float2 val = make_float2(acc[i][q][r], acc[i][q][r + 1]);
+          const f32x2 val = f32x2{acc[i][q][r], acc[i][q][r + 1]};
           if (FAN) {
             const int g = n >> d.nbits;
             const int jg = fj[g];  // uniform over the 32 lanes of a half-wave (one n)
             if (jg >= 0)
-              reinterpret_cast<float2*>(ws + d.c_off + (s * d.w + jg) * d.c_inst_bytes)
+              gmem<f32x2>(ws + d.c_off + (s * d.w + jg) * d.c_inst_bytes)
                   [om + tlook(tab + TAB_CN * kTabSize, n & nmask)] = val;
             if (REC) {
               // reduce over the half-wave's 32 values of m, one LDS atomic
@@ -223,9 +222,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
       if (tid < slots) {
         const int jg = fj[tid];
         if (jg >= 0) {
-          HalfScale* sc = reinterpret_cast<HalfScale*>(ws + d.c_scale_off) + (s * d.w + jg);
-          sc->e = 0;
-          if (s_mx[tid] > 0u) atomicMax(&sc->mx, s_mx[tid]);
+          stg_scale_e(ws + d.c_scale_off, s * d.w + jg, 0);
+          if (s_mx[tid] > 0u) max_scale_mx(ws + d.c_scale_off, s * d.w + jg, s_mx[tid]);
         }
       }
       __syncthreads();  // s_mx is cleared for the next tile
@@ -233,9 +231,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
       if (lane == 0) {
-        HalfScale* sc = reinterpret_cast<HalfScale*>(ws + d.c_scale_off) + inst;
-        sc->e = 0;
-        if (mx > 0.f) atomicMax(&sc->mx, __float_as_uint(mx));
+        stg_scale_e(ws + d.c_scale_off, inst, 0);
+        if (mx > 0.f) max_scale_mx(ws + d.c_scale_off, inst, __float_as_uint(mx));
       }
     }
   }
@@ -247,7 +244,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
 __global__ __launch_bounds__(256) void k_slice_sum(OpDesc root, uint64_t ws, const int64_t* __restrict__ sig,
                                                    int nb, int64_t nrows, const int32_t* __restrict__ rows,
                                                    int open_bits, double2* __restrict__ amps) {
-  const int32_t* __restrict__ gmap = reinterpret_cast<const int32_t*>(ws + root.gmap_off);
+  const gptr<const int32_t> gmap = gmem<const int32_t>(ws + root.gmap_off);
   const int64_t total = nrows << open_bits;
   const int64_t sigma0 = sig[0];
   const int64_t omask = ((int64_t)1 << open_bits) - 1;
@@ -258,7 +255,7 @@ __global__ __launch_bounds__(256) void k_slice_sum(OpDesc root, uint64_t ws, con
     double2 acc = amps[dst];
     for (int s = 0; s < nb; ++s) {
       const int64_t inst = operand_instance(root, gmap, rp, s, sigma0 + s);
-      const float2 v = reinterpret_cast<const float2*>(ws + root.off + inst * root.inst_bytes)[o];
+      const float2 v = ldg_f2(ws + root.off + inst * root.inst_bytes, o);
       acc.x += (double)v.x;
       acc.y += (double)v.y;
     }

@@ -31,13 +31,17 @@ bool chalf_available() { return true; }
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint32_t h2bits(__half2 h) { return *reinterpret_cast<uint32_t*>(&h); }
+__device__ __forceinline__ uint32_t h2bits(__half2 h) {
+  uint32_t u;
+  __builtin_memcpy(&u, &h, 4);
+  return u;
+}
 
 // element i of an operand as half2 bits: FP16 storage as is, FP32 storage
 // scaled by c and rounded to nearest
 __device__ __forceinline__ uint32_t ld_h2bits(uint64_t base, uint32_t i, int half, float c) {
-  if (half) return reinterpret_cast<const uint32_t*>(base)[i];
-  const float2 v = reinterpret_cast<const float2*>(base)[i];
+  if (half) return ldg_u32(base, i);
+  const float2 v = ldg_f2(base, i);
   return h2bits(__float22half2_rn(make_float2(v.x * c, v.y * c)));
 }
 
@@ -64,9 +68,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
   __shared__ float s_cb[FAN ? TN : 1];
   __shared__ uint32_t s_mx[FAN ? TN : 1];
 
-  const uint32_t* __restrict__ tab = reinterpret_cast<const uint32_t*>(ws + d.tab_off);
-  const int32_t* __restrict__ glA = reinterpret_cast<const int32_t*>(ws + d.A.gmap_off);
-  const int32_t* __restrict__ glB = reinterpret_cast<const int32_t*>(ws + d.B.gmap_off);
+  const gptr<const uint32_t> tab = gmem<const uint32_t>(ws + d.tab_off);
+  const gptr<const int32_t> glA = gmem<const int32_t>(ws + d.A.gmap_off);
+  const gptr<const int32_t> glB = gmem<const int32_t>(ws + d.B.gmap_off);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -82,10 +86,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
   const int dsel = l32 & 1;
   const int ncol = l32 >> 1;
   const int64_t units = FAN ? (d.n_inst / d.w) * d.n_fan : d.n_inst;
-  const int32_t* __restrict__ fan = reinterpret_cast<const int32_t*>(ws + d.fan_off);
+  const gptr<const int32_t> fan = gmem<const int32_t>(ws + d.fan_off);
   const uint32_t nmask = (1u << d.nbits) - 1u;
   const int slots = FAN ? (TN >> d.nbits) : 1;
-  const HalfScale* __restrict__ scB = reinterpret_cast<const HalfScale*>(ws + d.B.scale_off);
+  const uint64_t scB = ws + d.B.scale_off;
 
   for (int64_t blk = blockIdx.x; blk < units * tiles; blk += gridDim.x) {
     const int64_t u = blk / tiles;
@@ -93,7 +97,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
     const uint32_t m0 = (uint32_t)((t % mt_count) * TM);
     const uint32_t n0 = (uint32_t)((t / mt_count) * TN);
     int64_t s, j;
-    const int32_t* __restrict__ fj = nullptr;
+    gptr<const int32_t> fj = nullptr;
     if (FAN) {
       s = d.dep ? u / d.n_fan : 0;
       fj = fan + (u - s * d.n_fan) * slots;
@@ -108,11 +112,11 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
     const int64_t bi = operand_instance(d.B, glB, j, s, sigma);
     const uint64_t pa = ws + d.A.off + ai * d.A.inst_bytes;
     const uint64_t pb = ws + d.B.off + bi * d.B.inst_bytes;
-    __half2* __restrict__ pc = reinterpret_cast<__half2*>(ws + d.c_off + inst * d.c_inst_bytes);
+    const uint64_t pc = ws + d.c_off + inst * d.c_inst_bytes;
     // operand scales; an FP32 operand is converted on load with a power of two
     // that puts its largest component in [2^13, 2^14)
-    const HalfScale sa = reinterpret_cast<const HalfScale*>(ws + d.A.scale_off)[ai];
-    const HalfScale sb = reinterpret_cast<const HalfScale*>(ws + d.B.scale_off)[bi];
+    const HalfScale sa = ldg_scale(ws + d.A.scale_off, ai);
+    const HalfScale sb = ldg_scale(ws + d.B.scale_off, bi);
     int ea = sa.e, eb = sb.e;
     float mxa = __uint_as_float(sa.mx), mxb = __uint_as_float(sb.mx);
     float ca = 1.f, cb = 1.f;
@@ -138,7 +142,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
         float f = 0.f, cbg = 1.f;
         int e = 0;
         if (jg >= 0) {
-          const HalfScale sg = scB[operand_instance(d.B, glB, jg, s, sigma)];
+          const HalfScale sg = ldg_scale(scB, operand_instance(d.B, glB, jg, s, sigma));
           int ebg = sg.e;
           float mxbg = __uint_as_float(sg.mx);
           if (!hb && mxbg > 0.f) {
@@ -277,8 +281,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
             const float fg = s_f[g];
             const __half2 h = __float22half2_rn(make_float2(acc[i][q][r] * fg, acc[i][q][r + 1] * fg));
             if (jg >= 0)
-              reinterpret_cast<__half2*>(ws + d.c_off + (s * d.w + jg) * d.c_inst_bytes)
-                  [om + tlook(tab + TAB_CN * kTabSize, n & nmask)] = h;
+              stg_u32(ws + d.c_off + (s * d.w + jg) * d.c_inst_bytes, om + tlook(tab + TAB_CN * kTabSize, n & nmask),
+                      h2bits(h));
             const float2 back = __half22float2(h);
             float v = fmaxf(fabsf(back.x), fabsf(back.y));
 #pragma unroll
@@ -286,7 +290,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
             if (l32 == 0 && jg >= 0) atomicMax(&s_mx[g], __float_as_uint(v));
           } else {
             const __half2 h = __float22half2_rn(make_float2(acc[i][q][r] * f, acc[i][q][r + 1] * f));
-            pc[om + tlook(tab + TAB_CN * kTabSize, n)] = h;
+            stg_u32(pc, om + tlook(tab + TAB_CN * kTabSize, n), h2bits(h));
             const float2 back = __half22float2(h);
             mx = fmaxf(mx, fmaxf(fabsf(back.x), fabsf(back.y)));
           }
@@ -298,9 +302,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
       if (tid < slots) {
         const int jg = fj[tid];
         if (jg >= 0) {
-          HalfScale* sc = reinterpret_cast<HalfScale*>(ws + d.c_scale_off) + (s * d.w + jg);
-          sc->e = s_e[tid];
-          if (s_mx[tid] > 0u) atomicMax(&sc->mx, s_mx[tid]);
+          stg_scale_e(ws + d.c_scale_off, s * d.w + jg, s_e[tid]);
+          if (s_mx[tid] > 0u) max_scale_mx(ws + d.c_scale_off, s * d.w + jg, s_mx[tid]);
         }
       }
       __syncthreads();  // the slot arrays are rewritten by the next tile
@@ -308,9 +311,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
       if (lane == 0) {
-        HalfScale* sc = reinterpret_cast<HalfScale*>(ws + d.c_scale_off) + inst;
-        sc->e = e_out;
-        if (mx > 0.f) atomicMax(&sc->mx, __float_as_uint(mx));
+        stg_scale_e(ws + d.c_scale_off, inst, e_out);
+        if (mx > 0.f) max_scale_mx(ws + d.c_scale_off, inst, __float_as_uint(mx));
       }
     }
   }
@@ -319,8 +321,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
 __global__ __launch_bounds__(256) void k_slice_sum_h(OpDesc root, uint64_t ws, const int64_t* __restrict__ sig,
                                                      int nb, int64_t nrows, const int32_t* __restrict__ rows,
                                                      int open_bits, double2* __restrict__ amps) {
-  const int32_t* __restrict__ gmap = reinterpret_cast<const int32_t*>(ws + root.gmap_off);
-  const HalfScale* __restrict__ sc = reinterpret_cast<const HalfScale*>(ws + root.scale_off);
+  const gptr<const int32_t> gmap = gmem<const int32_t>(ws + root.gmap_off);
+  const uint64_t sc = ws + root.scale_off;
   const int64_t total = nrows << open_bits;
   const int64_t sigma0 = sig[0];
   const int64_t omask = ((int64_t)1 << open_bits) - 1;
@@ -332,9 +334,16 @@ __global__ __launch_bounds__(256) void k_slice_sum_h(OpDesc root, uint64_t ws, c
     for (int s = 0; s < nb; ++s) {
       const int64_t inst = operand_instance(root, gmap, rp, s, sigma0 + s);
       const uint64_t base = ws + root.off + inst * root.inst_bytes;
-      const float2 v = root.half ? __half22float2(reinterpret_cast<const __half2*>(base)[o])
-                                 : reinterpret_cast<const float2*>(base)[o];
-      const int e = sc[inst].e;
+      float2 v;
+      if (root.half) {
+        const uint32_t u = ldg_u32(base, o);
+        __half2 h;
+        __builtin_memcpy(&h, &u, 4);
+        v = __half22float2(h);
+      } else {
+        v = ldg_f2(base, o);
+      }
+      const int e = ldg_scale(sc, inst).e;
       acc.x += ldexp((double)v.x, e);
       acc.y += ldexp((double)v.y, e);
     }

@@ -39,8 +39,13 @@ constexpr int kMixBit = 8;
 
 template <int FL, int WHICH>
 __device__ __forceinline__ float2 ldop(uint64_t base, uint32_t i) {
-  if constexpr ((FL & kMixBit) && (FL & WHICH)) return __half22float2(reinterpret_cast<const __half2*>(base)[i]);
-  return reinterpret_cast<const float2*>(base)[i];
+  if constexpr ((FL & kMixBit) && (FL & WHICH)) {
+    const uint32_t u = ldg_u32(base, i);
+    __half2 h;
+    __builtin_memcpy(&h, &u, 4);
+    return __half22float2(h);
+  }
+  return ldg_f2(base, i);
 }
 
 // Output scale of one instance; identity for complex64 plans.
@@ -53,8 +58,8 @@ template <int FL>
 __device__ __forceinline__ OutScale out_scale(const NodeDesc& d, uint64_t ws, int64_t ai, int64_t bi) {
   OutScale o{1.f, 0};
   if constexpr ((FL & kMixBit) != 0) {
-    const HalfScale sa = reinterpret_cast<const HalfScale*>(ws + d.A.scale_off)[ai];
-    const HalfScale sb = reinterpret_cast<const HalfScale*>(ws + d.B.scale_off)[bi];
+    const HalfScale sa = ldg_scale(ws + d.A.scale_off, ai);
+    const HalfScale sb = ldg_scale(ws + d.B.scale_off, bi);
     if constexpr ((FL & 4) != 0) {
       const float bound = ldexpf(__uint_as_float(sa.mx) * __uint_as_float(sb.mx), d.kbits + 1);
       int ex = 0;
@@ -76,14 +81,16 @@ __device__ __forceinline__ float put(uint64_t base, uint32_t i, float2 c, const 
     const float2 v = make_float2(c.x * s.f, c.y * s.f);
     if constexpr ((FL & 4) != 0) {
       const __half2 h = __float22half2_rn(v);
-      reinterpret_cast<__half2*>(base)[i] = h;
+      uint32_t u;
+      __builtin_memcpy(&u, &h, 4);
+      stg_u32(base, i, u);
       const float2 back = __half22float2(h);
       return fmaxf(fabsf(back.x), fabsf(back.y));
     }
-    reinterpret_cast<float2*>(base)[i] = v;
+    stg_f2(base, i, v);
     return fmaxf(fabsf(v.x), fabsf(v.y));
   } else {
-    reinterpret_cast<float2*>(base)[i] = c;
+    stg_f2(base, i, c);
     return 0.f;
   }
 }
@@ -92,9 +99,8 @@ template <int FL>
 __device__ __forceinline__ void record_scale(const NodeDesc& d, uint64_t ws, int64_t inst, const OutScale& s,
                                              float mx, bool writer) {
   if constexpr ((FL & kMixBit) != 0) {
-    HalfScale* sc = reinterpret_cast<HalfScale*>(ws + d.c_scale_off) + inst;
-    if (writer) sc->e = s.e;
-    if (mx > 0.f) atomicMax(&sc->mx, __float_as_uint(mx));
+    if (writer) stg_scale_e(ws + d.c_scale_off, inst, s.e);
+    if (mx > 0.f) max_scale_mx(ws + d.c_scale_off, inst, __float_as_uint(mx));
   }
 }
 
@@ -131,8 +137,8 @@ __device__ __forceinline__ InstPtrs instance_ptrs(const NodeDesc& d, uint64_t ws
   r.inst = inst;
   const int64_t s = d.dep ? inst / d.w : 0;
   const int64_t j = d.dep ? inst - s * d.w : inst;
-  const int32_t* glA = reinterpret_cast<const int32_t*>(ws + d.A.gmap_off);
-  const int32_t* glB = reinterpret_cast<const int32_t*>(ws + d.B.gmap_off);
+  const gptr<const int32_t> glA = gmem<const int32_t>(ws + d.A.gmap_off);
+  const gptr<const int32_t> glB = gmem<const int32_t>(ws + d.B.gmap_off);
   r.ai = operand_instance(d.A, glA, j, s, sigma0 + s);
   r.bi = operand_instance(d.B, glB, j, s, sigma0 + s);
   r.pa = ws + d.A.off + (uint64_t)r.ai * d.A.inst_bytes;
@@ -149,9 +155,9 @@ __global__ __launch_bounds__(256) void k_wide(NodeDesc d, uint64_t ws, const int
   constexpr int LR = (R == 1) ? 0 : (R == 2) ? 1 : (R == 4) ? 2 : 3;
   __shared__ float2 Bs[KB * 16];
   __shared__ float red[4];
-  const uint32_t* __restrict__ tab = reinterpret_cast<const uint32_t*>(ws + d.tab_off);
-  const uint32_t* TA = tab + TAB_AM * kTabSize;
-  const uint32_t* TC = tab + TAB_CM * kTabSize;
+  const gptr<const uint32_t> tab = gmem<const uint32_t>(ws + d.tab_off);
+  const gptr<const uint32_t> TA = tab + TAB_AM * kTabSize;
+  const gptr<const uint32_t> TC = tab + TAB_CM * kTabSize;
   const int tid = threadIdx.x;
   const int NB = 1 << d.nbits;
   const uint32_t oa_lo = TA[tid], oc_lo = TC[tid];
@@ -204,7 +210,7 @@ __global__ __launch_bounds__(256) void k_wide(NodeDesc d, uint64_t ws, const int
 
 template <int FL, int KB>
 __global__ __launch_bounds__(256) void k_narrow(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
-  const uint32_t* __restrict__ tab = reinterpret_cast<const uint32_t*>(ws + d.tab_off);
+  const gptr<const uint32_t> tab = gmem<const uint32_t>(ws + d.tab_off);
   const int NB = 1 << d.nbits;
   uint32_t tak[KB], tbk[KB];
 #pragma unroll
@@ -258,7 +264,7 @@ __global__ __launch_bounds__(256) void k_kred(NodeDesc d, uint64_t ws, const int
   __shared__ uint32_t kofa[256], kofb[256];
   __shared__ float2 part[256 * NB];
   __shared__ float red[4];
-  const uint32_t* __restrict__ tab = reinterpret_cast<const uint32_t*>(ws + d.tab_off);
+  const gptr<const uint32_t> tab = gmem<const uint32_t>(ws + d.tab_off);
   const int tid = threadIdx.x;
   kofa[tid] = tab[TAB_AK * kTabSize + tid];
   kofb[tid] = tab[TAB_BK * kTabSize + tid];
@@ -341,7 +347,7 @@ __global__ __launch_bounds__(256) void k_kred(NodeDesc d, uint64_t ws, const int
 
 template <int FL>
 __global__ __launch_bounds__(256) void k_generic(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
-  const uint32_t* __restrict__ tab = reinterpret_cast<const uint32_t*>(ws + d.tab_off);
+  const gptr<const uint32_t> tab = gmem<const uint32_t>(ws + d.tab_off);
   const int cb = d.mbits + d.nbits;
   const int64_t total = d.n_inst << cb;
   const int64_t sigma0 = sig[0];
