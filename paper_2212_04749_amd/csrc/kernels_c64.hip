@@ -122,10 +122,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
       }
     }
     f32x2 ra[EA], rb[EB];
-    auto gload = [&](int ks) {
-      const uint32_t k0 = (uint32_t)ks * TK;
-      const uint32_t kba = tlook(tab + TAB_AK * kTabSize, k0);
-      const uint32_t kbb = tlook(tab + TAB_BK * kTabSize, k0);
+    auto gload = [&](uint32_t kba, uint32_t kbb) {
 #pragma unroll
       for (int e = 0; e < EA; ++e) ra[e] = pa[aoff[e] + kba];
 #pragma unroll
@@ -161,12 +158,42 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
     const float bsign = (half == 1 && dsel == 0) ? -1.f : 1.f;
     const int aplane = half ? APL : 0;
 
-    gload(0);
+    // output offsets of this lane (independent of k, fetched before the k
+    // loop): m of each row block, n of each accumulator register pair and,
+    // for fan tiles, the output instance of its slot
+    uint32_t om[RM], ocn[RN][8];
+    int32_t jgv[RN][8];
+#pragma unroll
+    for (int i = 0; i < RM; ++i) om[i] = tlook(tab + TAB_CM * kTabSize, m0 + (wm * RM + i) * 32 + l32);
+#pragma unroll
+    for (int q = 0; q < RN; ++q)
+#pragma unroll
+      for (int rr = 0; rr < 8; ++rr) {
+        const int row = 8 * (rr >> 1) + 4 * half + 2 * (rr & 1);
+        const uint32_t n = n0 + (wn * RN + q) * 16 + (row >> 1);
+        ocn[q][rr] = tlook(tab + TAB_CN * kTabSize, FAN ? (n & nmask) : n);
+        jgv[q][rr] = FAN ? fj[n >> d.nbits] : 0;
+      }
+
+    // k offsets run one step ahead of the loads that use them, so that their
+    // table reads are in flight during a whole step of MFMA work
+    uint32_t kba = tlook(tab + TAB_AK * kTabSize, 0u), kbb = tlook(tab + TAB_BK * kTabSize, 0u);
+    gload(kba, kbb);
+    if (ksteps > 1) {
+      kba = tlook(tab + TAB_AK * kTabSize, (uint32_t)TK);
+      kbb = tlook(tab + TAB_BK * kTabSize, (uint32_t)TK);
+    }
     lstore(0);
     __syncthreads();
     for (int ks = 0; ks < ksteps; ++ks) {
       const int buf = ks & 1;
-      if (ks + 1 < ksteps) gload(ks + 1);
+      if (ks + 1 < ksteps) {
+        gload(kba, kbb);
+        if (ks + 2 < ksteps) {
+          kba = tlook(tab + TAB_AK * kTabSize, (uint32_t)(ks + 2) * TK);
+          kbb = tlook(tab + TAB_BK * kTabSize, (uint32_t)(ks + 2) * TK);
+        }
+      }
 #pragma unroll
       for (int kk = 0; kk < TK; ++kk) {
         float yv[RM], xv[RN];
@@ -187,32 +214,34 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
     // epilogue: lane holds C[m][n] (re, im) in registers (r, r+1), r even
     float mx = 0.f;
 #pragma unroll
-    for (int i = 0; i < RM; ++i) {
-      const uint32_t m = m0 + (wm * RM + i) * 32 + l32;
-      const uint32_t om = tlook(tab + TAB_CM * kTabSize, m);
+    for (int q = 0; q < RN; ++q) {
 #pragma unroll
-      for (int q = 0; q < RN; ++q) {
+      for (int rr = 0; rr < 8; ++rr) {
+        const int r = 2 * rr;
+        gptr<f32x2> dst = pc;
+        bool live = true;
+        if (FAN) {
+          const int jg = jgv[q][rr];  // uniform over the 32 lanes of a half-wave (one n)
+          live = jg >= 0;
+          dst = gmem<f32x2>(ws + d.c_off + (s * d.w + (live ? jg : 0)) * d.c_inst_bytes);
+        }
+        float v = 0.f;
 #pragma unroll
-        for (int r = 0; r < 16; r += 2) {
-          const int row = 8 * (r >> 2) + 4 * half + (r & 3);
-          const uint32_t n = n0 + (wn * RN + q) * 16 + (row >> 1);
+        for (int i = 0; i < RM; ++i) {
           const f32x2 val = f32x2{acc[i][q][r], acc[i][q][r + 1]};
+          if (live) dst[om[i] + ocn[q][rr]] = val;
+          if (REC) v = fmaxf(v, fmaxf(fabsf(val.x), fabsf(val.y)));
+        }
+        if (REC) {
           if (FAN) {
-            const int g = n >> d.nbits;
-            const int jg = fj[g];  // uniform over the 32 lanes of a half-wave (one n)
-            if (jg >= 0)
-              gmem<f32x2>(ws + d.c_off + (s * d.w + jg) * d.c_inst_bytes)
-                  [om + tlook(tab + TAB_CN * kTabSize, n & nmask)] = val;
-            if (REC) {
-              // reduce over the half-wave's 32 values of m, one LDS atomic
-              float v = fmaxf(fabsf(val.x), fabsf(val.y));
+            // reduce over the half-wave's 32 values of m, one LDS atomic
 #pragma unroll
-              for (int o = 16; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-              if (l32 == 0 && jg >= 0) atomicMax(&s_mx[g], __float_as_uint(v));
-            }
+            for (int o = 16; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+            const int row = 8 * (rr >> 1) + 4 * half + 2 * (rr & 1);
+            const int g = (int)(((uint32_t)(wn * RN + q) * 16 + (row >> 1)) >> d.nbits);
+            if (l32 == 0 && live) atomicMax(&s_mx[g], __float_as_uint(v));
           } else {
-            pc[om + tlook(tab + TAB_CN * kTabSize, n)] = val;
-            if (REC) mx = fmaxf(mx, fmaxf(fabsf(acc[i][q][r]), fabsf(acc[i][q][r + 1])));
+            mx = fmaxf(mx, v);
           }
         }
       }

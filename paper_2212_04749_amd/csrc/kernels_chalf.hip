@@ -37,12 +37,24 @@ __device__ __forceinline__ uint32_t h2bits(__half2 h) {
   return u;
 }
 
-// element i of an operand as half2 bits: FP16 storage as is, FP32 storage
-// scaled by c and rounded to nearest
-__device__ __forceinline__ uint32_t ld_h2bits(uint64_t base, uint32_t i, int half, float c) {
-  if (half) return ldg_u32(base, i);
-  const float2 v = ldg_f2(base, i);
-  return h2bits(__float22half2_rn(make_float2(v.x * c, v.y * c)));
+__device__ __forceinline__ __half2 bits_h2(uint32_t u) {
+  __half2 h;
+  __builtin_memcpy(&h, &u, 4);
+  return h;
+}
+
+// element i of an operand as stored: a half2 in .x (FP16 storage) or the
+// two FP32 words
+__device__ __forceinline__ u32x2 ld_raw(uint64_t base, uint32_t i, int half) {
+  if (half) return u32x2{ldg_u32(base, i), 0u};
+  return gmem<const u32x2>(base)[i];
+}
+
+// as half2 bits: FP16 storage as is, FP32 storage scaled by c and rounded
+// to nearest
+__device__ __forceinline__ uint32_t to_h2bits(u32x2 raw, int half, float c) {
+  if (half) return raw.x;
+  return h2bits(__float22half2_rn(make_float2(__uint_as_float(raw.x) * c, __uint_as_float(raw.y) * c)));
 }
 
 // TM = 32*RM*WM values of m, TN = 16*RN*WN complex n, TK complex k (multiple of 4)
@@ -194,21 +206,22 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
         boff[e] = tlook(tab + TAB_BN * kTabSize, n0 + bnn[e]) + tab[TAB_BK * kTabSize + bkk[e]];
       }
     }
-    uint32_t ra[EA], rb[EB];
-    auto gload = [&](int ks) {
-      const uint32_t k0 = (uint32_t)ks * TK;
-      const uint32_t kba = tlook(tab + TAB_AK * kTabSize, k0);
-      const uint32_t kbb = tlook(tab + TAB_BK * kTabSize, k0);
+    // raw operand words in flight (an FP32 element, or a half2 in .x); the
+    // FP32 -> FP16 conversion happens when the tile is written to LDS, after
+    // the MFMA work of the current step, so the loads are not waited for
+    // inside the load phase
+    u32x2 ra[EA], rb[EB];
+    auto gload = [&](uint32_t kba, uint32_t kbb) {
 #pragma unroll
-      for (int e = 0; e < EA; ++e) ra[e] = ld_h2bits(pa, aoff[e] + kba, ha, ca);
+      for (int e = 0; e < EA; ++e) ra[e] = ld_raw(pa, aoff[e] + kba, ha);
 #pragma unroll
-      for (int e = 0; e < EB; ++e) rb[e] = (!FAN || pbe[e]) ? ld_h2bits(pbe[e], boff[e] + kbb, hb, cbe[e]) : 0u;
+      for (int e = 0; e < EB; ++e) rb[e] = (!FAN || pbe[e]) ? ld_raw(pbe[e], boff[e] + kbb, hb) : u32x2{0u, 0u};
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-      for (int e = 0; e < EA; ++e) As[buf][akk[e] * TM + amm[e]] = ra[e];
+      for (int e = 0; e < EA; ++e) As[buf][akk[e] * TM + amm[e]] = to_h2bits(ra[e], ha, ca);
 #pragma unroll
-      for (int e = 0; e < EB; ++e) Bs[buf][bkk[e] * TN + bnn[e]] = rb[e];
+      for (int e = 0; e < EB; ++e) Bs[buf][bkk[e] * TN + bnn[e]] = to_h2bits(rb[e], hb, cbe[e]);
     };
 
     floatx16 acc[RM][RN];
@@ -219,12 +232,39 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][q][r] = 0.f;
 
-    gload(0);
+    // output offsets of this lane, fetched before the k loop (see k_mfma)
+    uint32_t om[RM], ocn[RN][8];
+    int32_t jgv[RN][8];
+#pragma unroll
+    for (int i = 0; i < RM; ++i) om[i] = tlook(tab + TAB_CM * kTabSize, m0 + (wm * RM + i) * 32 + l32);
+#pragma unroll
+    for (int q = 0; q < RN; ++q)
+#pragma unroll
+      for (int rr = 0; rr < 8; ++rr) {
+        const int row = 8 * (rr >> 1) + 4 * half + 2 * (rr & 1);
+        const uint32_t n = n0 + (wn * RN + q) * 16 + (row >> 1);
+        ocn[q][rr] = tlook(tab + TAB_CN * kTabSize, FAN ? (n & nmask) : n);
+        jgv[q][rr] = FAN ? fj[n >> d.nbits] : 0;
+      }
+
+    // k offsets one step ahead of the loads that use them
+    uint32_t kba = tlook(tab + TAB_AK * kTabSize, 0u), kbb = tlook(tab + TAB_BK * kTabSize, 0u);
+    gload(kba, kbb);
+    if (ksteps > 1) {
+      kba = tlook(tab + TAB_AK * kTabSize, (uint32_t)TK);
+      kbb = tlook(tab + TAB_BK * kTabSize, (uint32_t)TK);
+    }
     lstore(0);
     __syncthreads();
     for (int ks = 0; ks < ksteps; ++ks) {
       const int buf = ks & 1;
-      if (ks + 1 < ksteps) gload(ks + 1);
+      if (ks + 1 < ksteps) {
+        gload(kba, kbb);
+        if (ks + 2 < ksteps) {
+          kba = tlook(tab + TAB_AK * kTabSize, (uint32_t)(ks + 2) * TK);
+          kbb = tlook(tab + TAB_BK * kTabSize, (uint32_t)(ks + 2) * TK);
+        }
+      }
 #pragma unroll
       for (int kq = 0; kq < TK; kq += 4) {
         const int k0 = kq + 2 * half;  // this lane's two complex k
@@ -232,18 +272,16 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
 #pragma unroll
         for (int i = 0; i < RM; ++i) {
           const int m = (wm * RM + i) * 32 + l32;
-          const uint32_t u0 = As[buf][k0 * TM + m], u1 = As[buf][(k0 + 1) * TM + m];
-          const __half2 h0 = *reinterpret_cast<const __half2*>(&u0);
-          const __half2 h1 = *reinterpret_cast<const __half2*>(&u1);
+          const __half2 h0 = bits_h2(As[buf][k0 * TM + m]);
+          const __half2 h1 = bits_h2(As[buf][(k0 + 1) * TM + m]);
           yv[i] = halfx4{(_Float16)__low2half(h0), (_Float16)__high2half(h0), (_Float16)__low2half(h1),
                          (_Float16)__high2half(h1)};
         }
 #pragma unroll
         for (int q = 0; q < RN; ++q) {
           const int n = (wn * RN + q) * 16 + ncol;
-          const uint32_t u0 = Bs[buf][k0 * TN + n], u1 = Bs[buf][(k0 + 1) * TN + n];
-          const __half2 h0 = *reinterpret_cast<const __half2*>(&u0);
-          const __half2 h1 = *reinterpret_cast<const __half2*>(&u1);
+          const __half2 h0 = bits_h2(Bs[buf][k0 * TN + n]);
+          const __half2 h1 = bits_h2(Bs[buf][(k0 + 1) * TN + n]);
           const _Float16 r0 = (_Float16)__low2half(h0), i0 = (_Float16)__high2half(h0);
           const _Float16 r1 = (_Float16)__low2half(h1), i1 = (_Float16)__high2half(h1);
           xv[q] = dsel ? halfx4{i0, r0, i1, r1} : halfx4{r0, -i0, r1, -i1};
@@ -266,34 +304,36 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
     const int e_out = ea + eb + ex - 15;
     float mx = 0.f;
 #pragma unroll
-    for (int i = 0; i < RM; ++i) {
-      const uint32_t m = m0 + (wm * RM + i) * 32 + l32;
-      const uint32_t om = tlook(tab + TAB_CM * kTabSize, m);
+    for (int q = 0; q < RN; ++q) {
 #pragma unroll
-      for (int q = 0; q < RN; ++q) {
+      for (int rr = 0; rr < 8; ++rr) {
+        const int r = 2 * rr;
+        uint64_t dst = pc;
+        bool live = true;
+        float fo = f;
+        int g = 0;
+        if (FAN) {
+          const int row = 8 * (rr >> 1) + 4 * half + 2 * (rr & 1);
+          g = (int)(((uint32_t)(wn * RN + q) * 16 + (row >> 1)) >> d.nbits);
+          const int jg = jgv[q][rr];  // uniform over the 32 lanes of a half-wave (one n)
+          live = jg >= 0;
+          dst = ws + d.c_off + (s * d.w + (live ? jg : 0)) * d.c_inst_bytes;
+          fo = s_f[g];
+        }
+        float v = 0.f;
 #pragma unroll
-        for (int r = 0; r < 16; r += 2) {
-          const int row = 8 * (r >> 2) + 4 * half + (r & 3);
-          const uint32_t n = n0 + (wn * RN + q) * 16 + (row >> 1);
-          if (FAN) {
-            const int g = n >> d.nbits;
-            const int jg = fj[g];  // uniform over the 32 lanes of a half-wave (one n)
-            const float fg = s_f[g];
-            const __half2 h = __float22half2_rn(make_float2(acc[i][q][r] * fg, acc[i][q][r + 1] * fg));
-            if (jg >= 0)
-              stg_u32(ws + d.c_off + (s * d.w + jg) * d.c_inst_bytes, om + tlook(tab + TAB_CN * kTabSize, n & nmask),
-                      h2bits(h));
-            const float2 back = __half22float2(h);
-            float v = fmaxf(fabsf(back.x), fabsf(back.y));
+        for (int i = 0; i < RM; ++i) {
+          const __half2 h = __float22half2_rn(make_float2(acc[i][q][r] * fo, acc[i][q][r + 1] * fo));
+          if (live) stg_u32(dst, om[i] + ocn[q][rr], h2bits(h));
+          const float2 back = __half22float2(h);
+          v = fmaxf(v, fmaxf(fabsf(back.x), fabsf(back.y)));
+        }
+        if (FAN) {
 #pragma unroll
-            for (int o2 = 16; o2 > 0; o2 >>= 1) v = fmaxf(v, __shfl_xor(v, o2));
-            if (l32 == 0 && jg >= 0) atomicMax(&s_mx[g], __float_as_uint(v));
-          } else {
-            const __half2 h = __float22half2_rn(make_float2(acc[i][q][r] * f, acc[i][q][r + 1] * f));
-            stg_u32(pc, om + tlook(tab + TAB_CN * kTabSize, n), h2bits(h));
-            const float2 back = __half22float2(h);
-            mx = fmaxf(mx, fmaxf(fabsf(back.x), fabsf(back.y)));
-          }
+          for (int o2 = 16; o2 > 0; o2 >>= 1) v = fmaxf(v, __shfl_xor(v, o2));
+          if (l32 == 0 && live) atomicMax(&s_mx[g], __float_as_uint(v));
+        } else {
+          mx = fmaxf(mx, v);
         }
       }
     }
