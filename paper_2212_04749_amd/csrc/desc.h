@@ -54,15 +54,15 @@ struct NodeDesc {
   int32_t c_half;        // complex-half plans: output stored as FP16 (1) or FP32 (0)
   // fan-out grouping (MFMA steps with few output columns whose A instance
   // is shared by several output instances): row g of the int32 table at
-  // fan_off lists up to kFanTileN >> nbits output instances j (-1 = empty
+  // fan_off lists up to fan_tn >> nbits output instances j (-1 = empty
   // slot) that all read the same A instance; they are computed together as
-  // one GEMM whose N columns are the slots' own B columns side by side
+  // one GEMM whose fan_tn columns are the slots' own B columns side by side
+  // (fan_tn = the N width of the tile configuration)
   uint64_t fan_off;
   int64_t n_fan;         // rows of the fan table (per slice)
+  int32_t fan_tn;
+  int32_t pad1;
 };
-
-// complex output columns of a fan-out tile (slots x 2^nbits)
-constexpr int kFanTileN = 32;
 
 // Scaling of one stored instance in complex-half plans: true value = stored
 // value * 2^e (e = 0 for FP32 storage); mx = largest |re| or |im| of the

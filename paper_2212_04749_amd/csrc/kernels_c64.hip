@@ -31,12 +31,10 @@ namespace matnc {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 // Tile: TM = 32*RM*WM values of m, TN = 16*RN*WN complex n, TK complex k.
-// REC: also record the output instance's largest |component| (complex-half
-// plans, whose FP32 stem tensors feed FP16 consumers).
 // FAN: the tile's TN columns are TN >> nbits slots of 2^nbits columns, one
 // per output instance of a fan-table row (see NodeDesc); the A tile is
 // loaded once for all of them.
-template <int RM, int RN, int WM, int WN, int TK, bool REC, bool FAN>
+template <int RM, int RN, int WM, int WN, int TK, bool FAN>
 __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
   constexpr int NT = 64 * WM * WN;
   constexpr int TM = 32 * RM * WM;
@@ -44,8 +42,6 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
   constexpr int EA = TK * TM / NT;
   constexpr int EB = TK * TN / NT;
   static_assert(EA * NT == TK * TM && EB * NT == TK * TN, "tile must split evenly over threads");
-  static_assert(!FAN || TN == kFanTileN, "fan-out tiles are kFanTileN columns wide");
-  __shared__ uint32_t s_mx[(REC && FAN) ? TN : 1];  // per-slot maxima (float bits)
   constexpr int APL = TK * TM + 32;        // plane stride (floats), padded
   constexpr int BPL = TK * TN + 16;
   __shared__ float As[2][2 * APL];
@@ -82,7 +78,6 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
       s = d.dep ? u / d.n_fan : 0;
       fj = fan + (u - s * d.n_fan) * slots;
       j = fj[0];
-      if (REC && tid < slots) s_mx[tid] = 0u;  // ordered before use by the first k-step barrier
     } else {
       s = d.dep ? u / d.w : 0;
       j = d.dep ? u - s * d.w : u;
@@ -212,7 +207,6 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
     }
 
     // epilogue: lane holds C[m][n] (re, im) in registers (r, r+1), r even
-    float mx = 0.f;
 #pragma unroll
     for (int q = 0; q < RN; ++q) {
 #pragma unroll
@@ -225,43 +219,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
           live = jg >= 0;
           dst = gmem<f32x2>(ws + d.c_off + (s * d.w + (live ? jg : 0)) * d.c_inst_bytes);
         }
-        float v = 0.f;
 #pragma unroll
-        for (int i = 0; i < RM; ++i) {
-          const f32x2 val = f32x2{acc[i][q][r], acc[i][q][r + 1]};
-          if (live) dst[om[i] + ocn[q][rr]] = val;
-          if (REC) v = fmaxf(v, fmaxf(fabsf(val.x), fabsf(val.y)));
-        }
-        if (REC) {
-          if (FAN) {
-            // reduce over the half-wave's 32 values of m, one LDS atomic
-#pragma unroll
-            for (int o = 16; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-            const int row = 8 * (rr >> 1) + 4 * half + 2 * (rr & 1);
-            const int g = (int)(((uint32_t)(wn * RN + q) * 16 + (row >> 1)) >> d.nbits);
-            if (l32 == 0 && live) atomicMax(&s_mx[g], __float_as_uint(v));
-          } else {
-            mx = fmaxf(mx, v);
-          }
-        }
-      }
-    }
-    if (REC && FAN) {
-      __syncthreads();
-      if (tid < slots) {
-        const int jg = fj[tid];
-        if (jg >= 0) {
-          stg_scale_e(ws + d.c_scale_off, s * d.w + jg, 0);
-          if (s_mx[tid] > 0u) max_scale_mx(ws + d.c_scale_off, s * d.w + jg, s_mx[tid]);
-        }
-      }
-      __syncthreads();  // s_mx is cleared for the next tile
-    } else if (REC) {
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-      if (lane == 0) {
-        stg_scale_e(ws + d.c_scale_off, inst, 0);
-        if (mx > 0.f) max_scale_mx(ws + d.c_scale_off, inst, __float_as_uint(mx));
+        for (int i = 0; i < RM; ++i)
+          if (live) dst[om[i] + ocn[q][rr]] = f32x2{acc[i][q][r], acc[i][q][r + 1]};
       }
     }
   }
@@ -325,6 +285,8 @@ static const MfmaCfg kMfmaCfgs[] = {
     {7, 6, 3},  // 1: RM=2 RN=2 WM=2 WN=2, TK=8  -> TM=128, TN=64
     {6, 5, 3},  // 2: RM=1 RN=1 WM=2 WN=2, TK=8  -> TM=64,  TN=32
     {8, 5, 3},  // 3: RM=4 RN=1 WM=2 WN=2, TK=8  -> TM=256, TN=32
+    {8, 6, 3},  // 4: RM=4 RN=2 WM=2 WN=2, TK=8  -> TM=256, TN=64
+    {7, 7, 3},  // 5: RM=2 RN=4 WM=2 WN=2, TK=8  -> TM=128, TN=128
 };
 
 int mfma_config_count() { return (int)(sizeof(kMfmaCfgs) / sizeof(kMfmaCfgs[0])); }
@@ -335,16 +297,18 @@ bool mfma_config_fits(int cfg, int mbits, int nbits, int kbits) {
   return mbits >= c.tm_bits && nbits >= c.tn_bits && kbits >= c.tk_bits;
 }
 
-bool mfma_fan_config_fits(int cfg, int mbits, int nbits, int kbits) {
+int mfma_config_tn(int cfg) { return cfg < 0 || cfg >= mfma_config_count() ? 0 : 1 << kMfmaCfgs[cfg].tn_bits; }
+
+bool mfma_fan_config_fits(int cfg, int mbits, int nbits, int kbits, int fan_tn) {
   if (cfg < 0 || cfg >= mfma_config_count()) return false;
   const MfmaCfg& c = kMfmaCfgs[cfg];
-  return (1 << c.tn_bits) == kFanTileN && nbits < c.tn_bits && mbits >= c.tm_bits && kbits >= c.tk_bits;
+  return (1 << c.tn_bits) == fan_tn && nbits < c.tn_bits && mbits >= c.tm_bits && kbits >= c.tk_bits;
 }
 
-template <bool REC, bool FAN>
+template <bool FAN>
 static hipError_t launch_mfma_t(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
   if (d.n_inst == 0) return hipSuccess;
-  const bool fits = FAN ? mfma_fan_config_fits(cfg, d.mbits, d.nbits, d.kbits)
+  const bool fits = FAN ? mfma_fan_config_fits(cfg, d.mbits, d.nbits, d.kbits, d.fan_tn)
                         : mfma_config_fits(cfg, d.mbits, d.nbits, d.kbits);
   if (!fits || (FAN && (d.w <= 0 || d.n_fan <= 0))) return hipErrorInvalidValue;
   const MfmaCfg& c = kMfmaCfgs[cfg];
@@ -352,32 +316,26 @@ static hipError_t launch_mfma_t(const NodeDesc& d, int cfg, uint64_t ws, const i
   const int64_t tiles = ((int64_t)1 << (d.mbits - c.tm_bits)) * (FAN ? 1 : ((int64_t)1 << (d.nbits - c.tn_bits)));
   const unsigned grid = grid_for(units * tiles);
   switch (cfg) {
-    case 0: hipLaunchKernelGGL((k_mfma<2, 1, 2, 2, 8, REC, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 1:
+    case 0: hipLaunchKernelGGL((k_mfma<2, 1, 2, 2, 8, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 1: hipLaunchKernelGGL((k_mfma<2, 2, 2, 2, 8, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 2: hipLaunchKernelGGL((k_mfma<1, 1, 2, 2, 8, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 3: hipLaunchKernelGGL((k_mfma<4, 1, 2, 2, 8, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 4: hipLaunchKernelGGL((k_mfma<4, 2, 2, 2, 8, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 5:
       if (FAN) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((k_mfma<2, 2, 2, 2, 8, REC, false>), dim3(grid), dim3(256), 0, st, d, ws, sig);
+      hipLaunchKernelGGL((k_mfma<2, 4, 2, 2, 8, false>), dim3(grid), dim3(256), 0, st, d, ws, sig);
       break;
-    case 2: hipLaunchKernelGGL((k_mfma<1, 1, 2, 2, 8, REC, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 3: hipLaunchKernelGGL((k_mfma<4, 1, 2, 2, 8, REC, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_mfma(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
-  return launch_mfma_t<false, false>(d, cfg, ws, sig, st);
-}
-
-hipError_t launch_mfma_rec(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
-  return launch_mfma_t<true, false>(d, cfg, ws, sig, st);
+  return launch_mfma_t<false>(d, cfg, ws, sig, st);
 }
 
 hipError_t launch_mfma_fan(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
-  return launch_mfma_t<false, true>(d, cfg, ws, sig, st);
-}
-
-hipError_t launch_mfma_fan_rec(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
-  return launch_mfma_t<true, true>(d, cfg, ws, sig, st);
+  return launch_mfma_t<true>(d, cfg, ws, sig, st);
 }
 
 hipError_t launch_slice_sum(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t nrows,

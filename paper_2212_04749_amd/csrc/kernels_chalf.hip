@@ -70,7 +70,6 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
   constexpr int EB = TK * TN / NT;
   static_assert(EA * NT == TK * TM && EB * NT == TK * TN, "tile must split evenly over threads");
   static_assert(TK % 4 == 0, "four complex k per instruction");
-  static_assert(!FAN || TN == kFanTileN, "fan-out tiles are kFanTileN columns wide");
   __shared__ uint32_t As[2][TK * TM];  // half2 bits, [k][m]
   __shared__ uint32_t Bs[2][TK * TN];  // half2 bits, [k][n]
   // fan-out slots: output factor, output exponent, FP32-load factor of B,
@@ -391,6 +390,33 @@ __global__ __launch_bounds__(256) void k_slice_sum_h(OpDesc root, uint64_t ws, c
   }
 }
 
+// one block per (instance, segment of up to 8192 elements): max over the
+// segment, one atomic per block
+__global__ __launch_bounds__(256) void k_absmax(uint64_t base, int ebits, int64_t n_inst, uint64_t scales) {
+  __shared__ float red[4];
+  const int sbits = ebits < 13 ? ebits : 13;
+  const int64_t seg_per_inst = (int64_t)1 << (ebits - sbits);
+  const int64_t n_blk = n_inst * seg_per_inst;
+  for (int64_t blk = blockIdx.x; blk < n_blk; blk += gridDim.x) {
+    const int64_t inst = blk / seg_per_inst;
+    const uint64_t e0 = ((uint64_t)inst << ebits) + ((uint64_t)(blk - inst * seg_per_inst) << sbits);
+    float mx = 0.f;
+    for (uint32_t e = threadIdx.x; e < (1u << sbits); e += 256) {
+      const float2 v = ldg_f2(base, e0 + e);
+      mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const float m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+      if (m > 0.f) max_scale_mx(scales, inst, __float_as_uint(m));
+    }
+    __syncthreads();  // red[] is rewritten by the next block
+  }
+}
+
 __global__ __launch_bounds__(256) void k_zero(uint4* __restrict__ p, int64_t n16) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (int64_t)gridDim.x * 256)
     p[i] = make_uint4(0u, 0u, 0u, 0u);
@@ -408,6 +434,8 @@ static const MfmaCfgH kMfmaCfgsH[] = {
     {6, 5, 4},  // 2: RM=1 RN=1 WM=2 WN=2, TK=16 -> TM=64,  TN=32
     {8, 5, 4},  // 3: RM=4 RN=1 WM=2 WN=2, TK=16 -> TM=256, TN=32
     {7, 5, 3},  // 4: RM=2 RN=1 WM=2 WN=2, TK=8  -> TM=128, TN=32
+    {8, 6, 4},  // 5: RM=4 RN=2 WM=2 WN=2, TK=16 -> TM=256, TN=64
+    {7, 6, 3},  // 6: RM=2 RN=2 WM=2 WN=2, TK=8  -> TM=128, TN=64
 };
 
 int mfma_h_config_count() { return (int)(sizeof(kMfmaCfgsH) / sizeof(kMfmaCfgsH[0])); }
@@ -418,16 +446,18 @@ bool mfma_h_config_fits(int cfg, int mbits, int nbits, int kbits) {
   return mbits >= c.tm_bits && nbits >= c.tn_bits && kbits >= c.tk_bits;
 }
 
-bool mfma_h_fan_config_fits(int cfg, int mbits, int nbits, int kbits) {
+int mfma_h_config_tn(int cfg) { return cfg < 0 || cfg >= mfma_h_config_count() ? 0 : 1 << kMfmaCfgsH[cfg].tn_bits; }
+
+bool mfma_h_fan_config_fits(int cfg, int mbits, int nbits, int kbits, int fan_tn) {
   if (cfg < 0 || cfg >= mfma_h_config_count()) return false;
   const MfmaCfgH& c = kMfmaCfgsH[cfg];
-  return (1 << c.tn_bits) == kFanTileN && nbits < c.tn_bits && mbits >= c.tm_bits && kbits >= c.tk_bits;
+  return (1 << c.tn_bits) == fan_tn && nbits < c.tn_bits && mbits >= c.tm_bits && kbits >= c.tk_bits;
 }
 
 template <bool FAN>
 static hipError_t launch_mfma_h_t(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
   if (d.n_inst == 0) return hipSuccess;
-  const bool fits = FAN ? mfma_h_fan_config_fits(cfg, d.mbits, d.nbits, d.kbits)
+  const bool fits = FAN ? mfma_h_fan_config_fits(cfg, d.mbits, d.nbits, d.kbits, d.fan_tn)
                         : mfma_h_config_fits(cfg, d.mbits, d.nbits, d.kbits);
   if (!fits || (FAN && (d.w <= 0 || d.n_fan <= 0))) return hipErrorInvalidValue;
   const MfmaCfgH& c = kMfmaCfgsH[cfg];
@@ -435,14 +465,13 @@ static hipError_t launch_mfma_h_t(const NodeDesc& d, int cfg, uint64_t ws, const
   const int64_t tiles = ((int64_t)1 << (d.mbits - c.tm_bits)) * (FAN ? 1 : ((int64_t)1 << (d.nbits - c.tn_bits)));
   const unsigned grid = grid_for(units * tiles);
   switch (cfg) {
-    case 0:
-      if (FAN) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((k_mfma_h<2, 2, 2, 2, 16, false>), dim3(grid), dim3(256), 0, st, d, ws, sig);
-      break;
+    case 0: hipLaunchKernelGGL((k_mfma_h<2, 2, 2, 2, 16, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
     case 1: hipLaunchKernelGGL((k_mfma_h<2, 1, 2, 2, 16, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
     case 2: hipLaunchKernelGGL((k_mfma_h<1, 1, 2, 2, 16, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
     case 3: hipLaunchKernelGGL((k_mfma_h<4, 1, 2, 2, 16, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
     case 4: hipLaunchKernelGGL((k_mfma_h<2, 1, 2, 2, 8, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 5: hipLaunchKernelGGL((k_mfma_h<4, 2, 2, 2, 16, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 6: hipLaunchKernelGGL((k_mfma_h<2, 2, 2, 2, 8, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -464,6 +493,16 @@ hipError_t launch_slice_sum_h(const OpDesc& root, uint64_t ws, const int64_t* si
   if (total == 0 || nb == 0) return hipSuccess;
   hipLaunchKernelGGL(k_slice_sum_h, dim3(grid_for((total + 255) / 256)), dim3(256), 0, st, root, ws, sig, nb, nrows,
                      rows, open_bits, reinterpret_cast<double2*>(amps));
+  return hipGetLastError();
+}
+
+hipError_t launch_absmax(const NodeDesc& d, uint64_t ws, hipStream_t st) {
+  if (d.n_inst == 0) return hipSuccess;
+  const int ebits = d.mbits + d.nbits;  // elements per output instance = 2^ebits (FP32 storage)
+  const int sbits = ebits < 13 ? ebits : 13;
+  const int64_t blocks = d.n_inst << (ebits - sbits);
+  hipLaunchKernelGGL(k_absmax, dim3(grid_for(blocks)), dim3(256), 0, st, ws + d.c_off, ebits, d.n_inst,
+                     ws + d.c_scale_off);
   return hipGetLastError();
 }
 

@@ -283,7 +283,7 @@ void build_steps(Plan& P) {
     const int mb = (int)V.M.size(), nb = (int)V.N.size(), kb = (int)V.K.size();
     V.kernel = 0;
     V.cfg = -1;
-    if (nb + kb > 8) {
+    if (nb + kb >= 8) {
       // MFMA tiles: prefer the widest N tile that fits
       if (!hm) {
         const int order[] = {1, 0, 3, 2};
@@ -309,23 +309,35 @@ void build_steps(Plan& P) {
     // instance is shared by others (or K is long enough that MFMA on
     // half-empty tiles still beats the vector units)
     V.fan = false;
-    V.fanv.clear();
-    V.n_fan = 0;
+    for (int t = 0; t < 2; ++t) {
+      V.fanv[t].clear();
+      V.n_fan[t] = 0;
+    }
     if (V.kernel == 0 && nb < 5 && kb >= 3 && mb >= 6) {
       std::vector<int32_t> ua(V.ga);
       std::sort(ua.begin(), ua.end());
       const double distinct = (double)(std::unique(ua.begin(), ua.end()) - ua.begin());
       const double reuse = (double)V.ga.size() / std::max(1.0, distinct);
       if (reuse >= 2.0 || (nb == 4 && kb >= 6)) {
-        const int order_f[] = {0, 3, 2, -1};
-        const int order_h[] = {1, 3, 2, 4};
-        for (int c : hm ? order_h : order_f) {
-          const bool fits = hm ? mfma_h_fan_config_fits(c, mb, nb, kb) : mfma_fan_config_fits(c, mb, nb, kb);
+        // 64-column tiles when the groups are large enough to fill them
+        // (the A tile is then read once for twice as many instances)
+        const int tn = (nb <= 4 && reuse >= 1.5 * (double)(32 >> nb)) ? 64 : 32;
+        const int order_f32[] = {0, 3, 2, -1};
+        const int order_f64[] = {4, 1, -1, -1};
+        const int order_h32[] = {1, 3, 2, 4};
+        const int order_h64[] = {5, 0, 6, -1};
+        const int* order = hm ? (tn == 64 ? order_h64 : order_h32) : (tn == 64 ? order_f64 : order_f32);
+        for (int t = 0; t < 4; ++t) {
+          const int c = order[t];
+          const bool fits = hm ? mfma_h_fan_config_fits(c, mb, nb, kb, tn) : mfma_fan_config_fits(c, mb, nb, kb, tn);
           if (fits) {
             V.kernel = 1;
             V.fan = true;
+            V.fan_tn = tn;
             V.cfg = c;
-            make_fan(V.ga, kFanTileN >> nb, V.fanv, V.n_fan);
+            // both tile widths' tables, so that the tuner may pick either
+            make_fan(V.ga, 32 >> nb, V.fanv[0], V.n_fan[0]);
+            make_fan(V.ga, 64 >> nb, V.fanv[1], V.n_fan[1]);
             break;
           }
         }
@@ -435,7 +447,10 @@ void build_chunks(Plan& P, int n_chunks) {
         N.ga.push_back(pa >= 0 ? find(local[pa], ua) : find(P.nodes[ca].keys, ua));
         N.gb.push_back(pb >= 0 ? find(local[pb], ub) : find(P.nodes[cb].keys, ub));
       }
-      if (V.fan) make_fan(N.ga, kFanTileN >> (int)V.N.size(), N.fanv, N.n_fan);
+      if (V.fan) {
+        make_fan(N.ga, 32 >> (int)V.N.size(), N.fanv[0], N.n_fan[0]);
+        make_fan(N.ga, 64 >> (int)V.N.size(), N.fanv[1], N.n_fan[1]);
+      }
     }
     // rows of the batch whose root key falls in this chunk
     const int rp = P.chunk_pos[root];
@@ -505,8 +520,10 @@ void build_memory_for(Plan& P, int n_chunks) {
       off = align_up(off + V.ga.size() * 4);
       V.gb_off = off;
       off = align_up(off + V.gb.size() * 4);
-      V.fan_off = off;
-      off = align_up(off + V.fanv.size() * 4);
+      for (int t = 0; t < 2; ++t) {
+        V.fan_off[t] = off;
+        off = align_up(off + V.fanv[t].size() * 4);
+      }
     }
   }
   // per-chunk index lists, packed back to back (int32 entries)
@@ -516,8 +533,10 @@ void build_memory_for(Plan& P, int n_chunks) {
       off += N.ga.size() * 4;
       N.gb_off = off;
       off += N.gb.size() * 4;
-      N.fan_off = off;
-      off += N.fanv.size() * 4;
+      for (int t = 0; t < 2; ++t) {
+        N.fan_off[t] = off;
+        off += N.fanv[t].size() * 4;
+      }
     }
     C.rows_off = off;
     off += C.rows.size() * 4;
@@ -732,8 +751,10 @@ NodeDesc node_desc(const Plan& P, int v, int nb, int c = 0) {
   d.nbits = (int32_t)V.N.size();
   d.kbits = (int32_t)V.K.size();
   if (V.fan) {
-    d.fan_off = pos >= 0 ? P.chunks[c].nodes[pos].fan_off : V.fan_off;
-    d.n_fan = pos >= 0 ? P.chunks[c].nodes[pos].n_fan : V.n_fan;
+    const int t = V.fan_tn == 64 ? 1 : 0;
+    d.fan_off = pos >= 0 ? P.chunks[c].nodes[pos].fan_off[t] : V.fan_off[t];
+    d.n_fan = pos >= 0 ? P.chunks[c].nodes[pos].n_fan[t] : V.n_fan[t];
+    d.fan_tn = V.fan_tn;
   }
   return d;
 }
@@ -747,16 +768,16 @@ OpDesc root_desc(const Plan& P, int c) {
 void launch_node(const Plan& P, const PNode& V, const NodeDesc& d, hipStream_t st) {
   const int64_t* sig = reinterpret_cast<const int64_t*>(P.ws + P.sigma_off);
   hipError_t e;
-  if (V.fan) {
-    e = V.half_store ? launch_mfma_h_fan(d, V.cfg, P.ws, sig, st)
-        : V.rec_max  ? launch_mfma_fan_rec(d, V.cfg, P.ws, sig, st)
-                     : launch_mfma_fan(d, V.cfg, P.ws, sig, st);
-  } else if (P.precision == MATNC_C64) {
-    e = V.kernel == 1 ? launch_mfma(d, V.cfg, P.ws, sig, st) : launch_stream(d, P.ws, sig, st);
+  if (V.kernel == 1 && !V.half_store) {
+    // FP32 MFMA; an FP16 consumer's scaling needs the output maxima, which
+    // a separate reduction pass records (cheaper than doing it in the GEMM
+    // epilogue, whose register use would cut the occupancy)
+    e = V.fan ? launch_mfma_fan(d, V.cfg, P.ws, sig, st) : launch_mfma(d, V.cfg, P.ws, sig, st);
+    if (e == hipSuccess && V.rec_max) e = launch_absmax(d, P.ws, st);
   } else if (V.kernel == 1) {
-    e = V.half_store ? launch_mfma_h(d, V.cfg, P.ws, sig, st)
-        : V.rec_max  ? launch_mfma_rec(d, V.cfg, P.ws, sig, st)
-                     : launch_mfma(d, V.cfg, P.ws, sig, st);
+    e = V.fan ? launch_mfma_h_fan(d, V.cfg, P.ws, sig, st) : launch_mfma_h(d, V.cfg, P.ws, sig, st);
+  } else if (P.precision == MATNC_C64) {
+    e = launch_stream(d, P.ws, sig, st);
   } else {
     // FP32 tensors whose maximum nobody reads take the complex64 kernels
     e = (V.half_store || V.rec_max) ? launch_stream_h(d, P.ws, sig, st) : launch_stream(d, P.ws, sig, st);
@@ -849,7 +870,8 @@ void launch_pass(Plan& P, int64_t b, int64_t e, double* amps, hipStream_t st) {
 std::string tune_key(const Plan& P, const PNode& V, int64_t n_inst) {
   int lg = 0;
   while ((1LL << lg) < n_inst) ++lg;
-  return std::string(P.precision == MATNC_C64 ? "c64" : "chalf") + (V.half_store ? "/h" : V.fan ? "/fan" : "/f") + "/" +
+  return std::string(P.precision == MATNC_C64 ? "c64" : "chalf") + (V.half_store ? "/h" : "/f") +
+         (V.fan ? "/fan" : "") + "/" +
          std::to_string(V.M.size()) + "," + std::to_string(V.N.size()) + "," + std::to_string(V.K.size()) + "/" +
          std::to_string(lg);
 }
@@ -1109,14 +1131,16 @@ int matnc_plan_bind(matnc_plan plan, void* dev_workspace, size_t bytes, void* hi
       if (P.chunk_pos[v] < 0) {
         std::memcpy(P.staging.data() + V.ga_off, V.ga.data(), V.ga.size() * 4);
         std::memcpy(P.staging.data() + V.gb_off, V.gb.data(), V.gb.size() * 4);
-        std::memcpy(P.staging.data() + V.fan_off, V.fanv.data(), V.fanv.size() * 4);
+        for (int t = 0; t < 2; ++t)
+          std::memcpy(P.staging.data() + V.fan_off[t], V.fanv[t].data(), V.fanv[t].size() * 4);
       }
     }
     for (const Chunk& C : P.chunks) {
       for (const ChunkNode& N : C.nodes) {
         std::memcpy(P.staging.data() + N.ga_off, N.ga.data(), N.ga.size() * 4);
         std::memcpy(P.staging.data() + N.gb_off, N.gb.data(), N.gb.size() * 4);
-        std::memcpy(P.staging.data() + N.fan_off, N.fanv.data(), N.fanv.size() * 4);
+        for (int t = 0; t < 2; ++t)
+          std::memcpy(P.staging.data() + N.fan_off[t], N.fanv[t].data(), N.fanv[t].size() * 4);
       }
       std::memcpy(P.staging.data() + C.rows_off, C.rows.data(), C.rows.size() * 4);
       std::memcpy(P.staging.data() + C.rootloc_off, C.rootloc.data(), C.rootloc.size() * 4);
@@ -1209,20 +1233,29 @@ int matnc_plan_autotune(matnc_plan plan, int reps, const char* cache_path) {
     for (int v : order) {
       PNode& V = P.nodes[v];
       if (V.kernel != 1) continue;
-      const NodeDesc d0 = node_desc(P, v, V.dep ? P.batch : 1);
-      const std::string key = tune_key(P, V, d0.n_inst);
+      const std::string key = tune_key(P, V, node_desc(P, v, V.dep ? P.batch : 1).n_inst);
       auto it = cache.find(key);
       const bool half = V.half_store;  // FP16-product MFMA kernels
       const int ncfg = half ? mfma_h_config_count() : mfma_config_count();
       const int mb = (int)V.M.size(), nb = (int)V.N.size(), kb = (int)V.K.size();
+      // fan-out steps: the configuration's N width picks the fan table
+      auto cfg_tn = [&](int c) { return half ? mfma_h_config_tn(c) : mfma_config_tn(c); };
       auto config_fits = [&](int c) {
-        if (V.fan) return half ? mfma_h_fan_config_fits(c, mb, nb, kb) : mfma_fan_config_fits(c, mb, nb, kb);
+        if (V.fan) {
+          const int tn = cfg_tn(c);
+          if (tn != 32 && tn != 64) return false;
+          return half ? mfma_h_fan_config_fits(c, mb, nb, kb, tn) : mfma_fan_config_fits(c, mb, nb, kb, tn);
+        }
         return half ? mfma_h_config_fits(c, mb, nb, kb) : mfma_config_fits(c, mb, nb, kb);
+      };
+      auto use = [&](int c) {
+        V.cfg = c;
+        if (V.fan) V.fan_tn = cfg_tn(c);
       };
       if (it != cache.end()) {
         const bool fits = config_fits(it->second);
         if (fits) {
-          V.cfg = it->second;
+          use(it->second);
           continue;
         }
       }
@@ -1231,7 +1264,8 @@ int matnc_plan_autotune(matnc_plan plan, int reps, const char* cache_path) {
       bool have = false;
       for (int c = 0; c < ncfg; ++c) {
         if (!config_fits(c)) continue;
-        V.cfg = c;
+        use(c);
+        const NodeDesc d0 = node_desc(P, v, V.dep ? P.batch : 1);
         launch_node(P, V, d0, st);  // warm-up
         hip_check(hipEventRecord(e0, st), "event record");
         for (int r = 0; r < reps; ++r) launch_node(P, V, d0, st);
@@ -1245,7 +1279,7 @@ int matnc_plan_autotune(matnc_plan plan, int reps, const char* cache_path) {
           best_cfg = c;
         }
       }
-      V.cfg = best_cfg;
+      use(best_cfg);
       cache[key] = best_cfg;
     }
     hip_check(hipStreamSynchronize(st), "autotune sync");

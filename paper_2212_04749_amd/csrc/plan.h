@@ -52,9 +52,10 @@ struct PNode {
   int kernel = 0;                // 0 streaming, 1 MFMA
   int cfg = -1;
   bool fan = false;              // MFMA step run as fan-out tiles (rows of fanv)
-  std::vector<int32_t> fanv;     // fan table (unchunked plans)
-  int64_t n_fan = 0;
-  uint64_t fan_off = 0;
+  int fan_tn = 0;                // complex columns of its tiles (slots x 2^|N|): 32 or 64
+  std::vector<int32_t> fanv[2];  // fan tables for 32- and 64-column tiles (unchunked plans)
+  int64_t n_fan[2] = {0, 0};
+  uint64_t fan_off[2] = {0, 0};
   std::vector<int> M, N, K;      // virtual orders of the three index classes
   // memory
   uint64_t inst_elems = 0;
@@ -74,9 +75,9 @@ struct ChunkNode {
   int32_t w = 0;                      // this chunk's instances of the node
   std::vector<int32_t> ga, gb;        // gather maps (local or full child indices)
   uint64_t ga_off = 0, gb_off = 0;
-  std::vector<int32_t> fanv;          // fan table over this chunk's instances
-  int64_t n_fan = 0;
-  uint64_t fan_off = 0;
+  std::vector<int32_t> fanv[2];       // fan tables over this chunk's instances (32, 64 columns)
+  int64_t n_fan[2] = {0, 0};
+  uint64_t fan_off[2] = {0, 0};
 };
 
 struct Chunk {

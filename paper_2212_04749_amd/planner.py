@@ -147,7 +147,7 @@ def step_time(w: float, wa: float, wb: float, ra: int, rb: int, rc: int, k: int)
     flops = 8.0 * w * 2.0 ** (m + n + k)
     by = 8.0 * (w * 2.0 ** rc + wa * 2.0 ** ra + wb * 2.0 ** rb)
     rate = RATE_VALU
-    if n + k > 8 and m >= 6 and n >= 5 and k >= 3:
+    if n + k >= 8 and m >= 6 and n >= 5 and k >= 3:
         rate = RATE_MFMA
     elif m >= 6 and k >= 3 and n < 5:
         # fan-out tiles: output instances sharing an A instance fill the
@@ -456,7 +456,8 @@ class Plan:
 
 
 def refine(st: Structure, plan: Plan, words: np.ndarray, cap: Optional[int],
-           exact_slices: Optional[int] = None, rounds: int = 4, objective: str = "time") -> Plan:
+           exact_slices: Optional[int] = None, rounds: int = 4, objective: str = "time",
+           min_slices: int = 0) -> Plan:
     """Alternate subtree reconfiguration (sizes 6, 8, 10) with re-slicing
     until the objective stops falling."""
     best = plan
@@ -471,7 +472,7 @@ def refine(st: Structure, plan: Plan, words: np.ndarray, cap: Optional[int],
         c = costs(st, build_tree(st, pairs, sl), w, sl)
         cand = Plan(pairs, sliced, c, w, best.method + "+reconf")
         try:
-            s2, c2 = slice_to_cap(st, pairs, w, cap, min_slices=exact_slices or 0, objective=objective)
+            s2, c2 = slice_to_cap(st, pairs, w, cap, min_slices=exact_slices or min_slices, objective=objective)
             if (exact_slices is None or len(s2) == exact_slices) and c2.score(objective) < c.score(objective):
                 cand = Plan(pairs, s2, c2, w, best.method + "+reconf")
         except ValueError:
@@ -489,7 +490,7 @@ def find_plan(net: TensorNetwork, words: np.ndarray, open_qubits: Sequence[int] 
               min_slices: int = 0, exact_slices: Optional[int] = None,
               include_greedy: bool = True, refine_top: int = 3, partition_trials: int = 0,
               rgreedy_trials: int = 0, timeline: bool = False, max_sliced: int = 40,
-              objective: str = "time") -> Plan:
+              objective: str = "time", progress=None) -> Plan:
     """Search candidate orders; slice each to the cap; refine the cheapest
     few by subtree reconfiguration; keep the cheapest under ``objective``
     ("time" or "flops", see the module docstring)."""
@@ -518,7 +519,9 @@ def find_plan(net: TensorNetwork, words: np.ndarray, open_qubits: Sequence[int] 
         imb = float(rng.uniform(0.05, 0.35))
         candidates.append((f"bisection[{t}]", partition_pairs(st, rng, imb)))
     scored = []
-    for name, pairs in candidates:
+    for ci, (name, pairs) in enumerate(candidates):
+        if progress is not None:
+            progress(f"candidate {ci + 1}/{len(candidates)}")
         tree = build_tree(st, pairs)
         w = widths(tree, words)
         try:
@@ -536,13 +539,15 @@ def find_plan(net: TensorNetwork, words: np.ndarray, open_qubits: Sequence[int] 
     scored.sort(key=lambda x: x[0])
     out = []
     for key, pl in scored[:max(1, refine_top)]:
+        if progress is not None:
+            progress(f"refining {pl.method}")
         r = pl
         if refine_top > 0:
             # the flop objective's local search first (it escapes the poor
             # initial shapes best), then the time objective from there
-            r = refine(st, pl, words, cap, exact_slices, objective="flops")
+            r = refine(st, pl, words, cap, exact_slices, objective="flops", min_slices=min_slices)
             if objective == "time":
-                r = refine(st, r, words, cap, exact_slices, objective="time")
+                r = refine(st, r, words, cap, exact_slices, objective="time", min_slices=min_slices)
         miss = 0 if exact_slices is None else abs(len(r.sliced) - exact_slices)
         out.append(((miss, r.costs.score(objective), r.costs.max_rank), r))
     out.sort(key=lambda x: x[0])
