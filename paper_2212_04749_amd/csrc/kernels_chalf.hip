@@ -70,8 +70,13 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
   constexpr int EB = TK * TN / NT;
   static_assert(EA * NT == TK * TM && EB * NT == TK * TN, "tile must split evenly over threads");
   static_assert(TK % 4 == 0, "four complex k per instruction");
-  __shared__ uint32_t As[2][TK * TM];  // half2 bits, [k][m]
-  __shared__ uint32_t Bs[2][TK * TN];  // half2 bits, [k][n]
+  // LDS tiles in the register layout of the MFMA operands, so that each
+  // operand is one 8-byte LDS read: As[k/2][m][k%2] holds A's half2 (re, im);
+  // Bs[k/2][n][d][k%2] holds B's column pair of the real embedding, (re, -im)
+  // for d = 0 and (im, re) for d = 1
+  constexpr int APAIR = 2 * TM + 8;  // u32 per k pair (padded)
+  __shared__ __attribute__((aligned(16))) uint32_t As[2][(TK / 2) * APAIR];
+  __shared__ __attribute__((aligned(16))) uint32_t Bs[2][(TK / 2) * TN * 4];
   // fan-out slots: output factor, output exponent, FP32-load factor of B,
   // recorded maximum (float bits)
   __shared__ float s_f[FAN ? TN : 1];
@@ -218,9 +223,16 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-      for (int e = 0; e < EA; ++e) As[buf][akk[e] * TM + amm[e]] = to_h2bits(ra[e], ha, ca);
+      for (int e = 0; e < EA; ++e)
+        As[buf][(akk[e] >> 1) * APAIR + 2 * amm[e] + (akk[e] & 1)] = to_h2bits(ra[e], ha, ca);
 #pragma unroll
-      for (int e = 0; e < EB; ++e) Bs[buf][bkk[e] * TN + bnn[e]] = to_h2bits(rb[e], hb, cbe[e]);
+      for (int e = 0; e < EB; ++e) {
+        const uint32_t h = to_h2bits(rb[e], hb, cbe[e]);
+        const uint32_t re = h & 0xffffu, im = h >> 16;
+        const int base = (((bkk[e] >> 1) * TN + bnn[e]) * 2) * 2 + (bkk[e] & 1);
+        Bs[buf][base] = re | ((im ^ 0x8000u) << 16);  // (Br, -Bi)
+        Bs[buf][base + 2] = im | (re << 16);           // (Bi, Br)
+      }
     };
 
     floatx16 acc[RM][RN];
@@ -266,24 +278,17 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
       }
 #pragma unroll
       for (int kq = 0; kq < TK; kq += 4) {
-        const int k0 = kq + 2 * half;  // this lane's two complex k
+        const int kp = (kq >> 1) + half;  // this lane's pair of complex k
         halfx4 yv[RM], xv[RN];
 #pragma unroll
         for (int i = 0; i < RM; ++i) {
           const int m = (wm * RM + i) * 32 + l32;
-          const __half2 h0 = bits_h2(As[buf][k0 * TM + m]);
-          const __half2 h1 = bits_h2(As[buf][(k0 + 1) * TM + m]);
-          yv[i] = halfx4{(_Float16)__low2half(h0), (_Float16)__high2half(h0), (_Float16)__low2half(h1),
-                         (_Float16)__high2half(h1)};
+          yv[i] = *reinterpret_cast<const halfx4*>(&As[buf][kp * APAIR + 2 * m]);
         }
 #pragma unroll
         for (int q = 0; q < RN; ++q) {
           const int n = (wn * RN + q) * 16 + ncol;
-          const __half2 h0 = bits_h2(Bs[buf][k0 * TN + n]);
-          const __half2 h1 = bits_h2(Bs[buf][(k0 + 1) * TN + n]);
-          const _Float16 r0 = (_Float16)__low2half(h0), i0 = (_Float16)__high2half(h0);
-          const _Float16 r1 = (_Float16)__low2half(h1), i1 = (_Float16)__high2half(h1);
-          xv[q] = dsel ? halfx4{i0, r0, i1, r1} : halfx4{r0, -i0, r1, -i1};
+          xv[q] = *reinterpret_cast<const halfx4*>(&Bs[buf][((kp * TN + n) * 2 + dsel) * 2]);
         }
 #pragma unroll
         for (int i = 0; i < RM; ++i)
