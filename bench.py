@@ -42,7 +42,9 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4"])
+    p.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4", "C5"])
+    p.add_argument("--max-est-s", type=float, default=20.0,
+                   help="uneven batch (C5): leave out circuits whose plan's estimated time exceeds this")
     p.add_argument("--precision", default="c64", choices=["c64", "chalf"])
     p.add_argument("--slice-batch", type=int, default=0, help="0 = workload default")
     p.add_argument("--trials", type=int, default=32, help="order-search candidates")
@@ -197,6 +199,101 @@ def cpu_baseline(name, w):
                       f"{t_full:.1f} s for all {w.k} bitstrings"}
 
 
+def run_uneven(args) -> None:
+    """The uneven batch: the 32 seeded circuits of workload.configs with the
+    stored plans (plans/c5_cap30.json), in complex-half by default. Plans
+    are packed, largest workspace first, into groups whose workspaces fit
+    the device memory; each group is one queue (one captured graph of all
+    of its plans' launches, slice-sums and XEBs). The timed step replays
+    every group's queue once; amplitudes/s counts every amplitude of every
+    circuit in the batch."""
+    import torch
+    from paper_2212_04749_amd import api, binding as B
+    from paper_2212_04749_amd.circuit_tn import build_network
+    from paper_2212_04749_amd.plans import make_c5
+    from workload.configs import uneven_batch_c5
+
+    plans = make_c5.load()
+    prec = args.precision
+    sel, skipped = [], []
+    for w in uneven_batch_c5():
+        e = plans[w.name]
+        (sel if e["est_seconds"] <= args.max_est_s else skipped).append((w, e))
+    free, _ = torch.cuda.mem_get_info()
+    cap_bytes = int(0.85 * free)
+    # workspace each plan needs (chunked down to the device budget if larger)
+    items = []
+    for w, e in sel:
+        net = build_network(w.circuit())
+        ranks, ids, data = api.network_arrays(net)
+        h = B.matnc_network_create(ranks, ids, data, net.n_qubits, net.output_index)
+        p = B.matnc_plan_create(h, [tuple(x) for x in e["pairs"]], e["sliced"], [], w.bitstrings(),
+                                api.PRECISIONS[prec], e["cap"], 1, cap_bytes)
+        need = int(B.matnc_plan_info(p).workspace_bytes)
+        B.matnc_plan_destroy(p)
+        B.matnc_network_destroy(h)
+        items.append((need, w, e, net))
+    items.sort(key=lambda x: -x[0])
+    groups = []
+    for it in items:  # first fit, largest first
+        for g in groups:
+            if g["bytes"] + it[0] <= cap_bytes:
+                g["items"].append(it)
+                g["bytes"] += it[0]
+                break
+        else:
+            groups.append({"bytes": it[0], "items": [it]})
+    log(f"uneven batch: {len(sel)} circuits in {len(groups)} queue groups, {len(skipped)} left out "
+        f"(estimated over {args.max_est_s} s each)")
+    total_ms = 0.0
+    xebs, n_amps, cmac = {}, 0, 0.0
+    stream = torch.cuda.Stream()
+    for gi, g in enumerate(groups):
+        runs = []
+        for need, w, e, net in g["items"]:
+            spec = api.PlanSpec([tuple(x) for x in e["pairs"]], e["sliced"], (), e["cap"])
+            runs.append(api.Contraction(net, spec, w.bitstrings(), precision=prec, slice_batch=1, stream=stream,
+                                        memory_budget=need))
+        q = api.Queue(runs)
+        amps, xeb = q.execute()  # capture
+        for _ in range(args.warmup):
+            q.execute(amps, xeb)
+        stream.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            q.execute(amps, xeb)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        total_ms += ms
+        xs = xeb.cpu().numpy()
+        for (need, w, e, net), r, x in zip(g["items"], runs, xs):
+            xebs[w.name] = float(x)
+            n_amps += r.k
+            cmac += r.info.cmac_total
+        log(f"group {gi}: {len(runs)} circuits, {g['bytes'] / 2**30:.1f} GiB, {ms:.2f} ms per pass")
+        q.close()
+        for r in runs:
+            r.close()
+        del amps, xeb
+        torch.cuda.empty_cache()
+    secs = total_ms / 1e3
+    out = {
+        "metric": "sustained complex TFLOP/s + amplitudes/sec per slice-batch at stated err vs FP64",
+        "value": n_amps / secs, "unit": "amplitudes/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": total_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "complex64" if prec == "c64" else "complex-half", "data": "synthetic",
+        "complex_tflops": 8 * cmac / secs / 1e12,
+        "config": {"workload": f"C5: uneven batch of {len(sel)} seeded grid RQCs (20-36 qubits, depth 10-16, "
+                               f"256-4096 bitstrings), stored plans at rank cap 30, one queue per memory group",
+                   "circuits": len(sel), "left_out": [w.name for w, _ in skipped], "groups": len(groups),
+                   "amplitudes": n_amps, "precision": prec},
+        "xeb_per_circuit": xebs,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -211,6 +308,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if args.workload == "C5":
+        run_uneven(args)
+        return
     from paper_2212_04749_amd import api, planner
     from paper_2212_04749_amd.circuit_tn import build_network
     from workload import CONFIGS

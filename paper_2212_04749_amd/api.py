@@ -233,13 +233,19 @@ class Queue:
         self._q = B.matnc_queue_create([r._plan for r in self.runs])
         self.stream = self.runs[0].stream
 
-    def execute(self):
-        """Fresh zeroed amplitude buffers, one pass of every plan; returns
-        (list of amplitude tensors, XEB tensor)."""
+    def execute(self, amps=None, xeb=None):
+        """One pass of every plan; returns (list of amplitude tensors, XEB
+        tensor).  Without buffers, fresh zeroed ones are allocated; given
+        buffers (from an earlier call) are zeroed on the queue's stream and
+        reused, so that the captured graph is replayed, not re-captured."""
         import torch
         with torch.cuda.stream(self.stream):
-            amps = [r.new_amplitudes() for r in self.runs]
-            xeb = torch.zeros(len(self.runs), dtype=torch.float64, device=self.runs[0].device)
+            if amps is None:
+                amps = [r.new_amplitudes() for r in self.runs]
+                xeb = torch.zeros(len(self.runs), dtype=torch.float64, device=self.runs[0].device)
+            else:
+                for a in amps:
+                    a.zero_()
         B.matnc_queue_execute(self._q, [a.data_ptr() for a in amps], xeb.data_ptr())
         return amps, xeb
 
