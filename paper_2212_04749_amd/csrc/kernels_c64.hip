@@ -46,6 +46,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
   constexpr int BPL = TK * TN + 16;
   __shared__ float As[2][2 * APL];
   __shared__ float Bs[2][2 * BPL];
+  // per-tile column data, shared by the waves instead of held per lane:
+  // the C offset of each of the tile's TN columns, and for fan tiles the
+  // B instance (byte offset) and output instance base of each slot
+  __shared__ uint32_t s_cn[TN];
+  __shared__ uint64_t s_bb[FAN ? TN : 1];
+  __shared__ uint64_t s_cb[FAN ? TN : 1];
 
   const gptr<const uint32_t> tab = gmem<const uint32_t>(ws + d.tab_off);
   const gptr<const int32_t> glA = gmem<const int32_t>(ws + d.A.gmap_off);
@@ -89,6 +95,14 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
     const gptr<const f32x2> pa = gmem<const f32x2>(ws + d.A.off + ai * d.A.inst_bytes);
     const gptr<const f32x2> pb = gmem<const f32x2>(ws + d.B.off + bi * d.B.inst_bytes);
     const gptr<f32x2> pc = gmem<f32x2>(ws + d.c_off + inst * d.c_inst_bytes);
+    if (tid < TN) s_cn[tid] = tlook(tab + TAB_CN * kTabSize, FAN ? (tid & nmask) : n0 + tid);
+    if (FAN && tid < slots) {
+      // an empty slot reads slot 0's B into columns that are never stored
+      const int jg = fj[tid];
+      s_bb[tid] = d.B.off + operand_instance(d.B, glB, jg < 0 ? j : jg, s, sigma) * d.B.inst_bytes;
+      s_cb[tid] = jg < 0 ? 0 : d.c_off + (uint64_t)(s * d.w + jg) * d.c_inst_bytes;
+    }
+    __syncthreads();  // the column data above is read by every wave
 
     // per-thread load coordinates (fixed across k steps)
     uint32_t aoff[EA], boff[EB];
@@ -100,7 +114,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
       akk[e] = flat / TM;
       aoff[e] = tlook(tab + TAB_AM * kTabSize, m0 + amm[e]) + tab[TAB_AK * kTabSize + akk[e]];
     }
-    gptr<const f32x2> pbe[EB];  // fan tiles: B instance of each element's slot (null: empty slot)
+    gptr<const f32x2> pbe[EB];  // B instance of each element (fan tiles: its slot's)
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const int flat = e * NT + tid;
@@ -108,8 +122,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
       bkk[e] = flat / TN;
       if (FAN) {
         const int jg = fj[bnn[e] >> d.nbits];
-        pbe[e] = jg < 0 ? nullptr
-                        : gmem<const f32x2>(ws + d.B.off + operand_instance(d.B, glB, jg, s, sigma) * d.B.inst_bytes);
+        pbe[e] = gmem<const f32x2>(ws + s_bb[bnn[e] >> d.nbits]);
         boff[e] = tlook(tab + TAB_BN * kTabSize, bnn[e] & nmask) + tab[TAB_BK * kTabSize + bkk[e]];
       } else {
         pbe[e] = pb;
@@ -121,7 +134,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
 #pragma unroll
       for (int e = 0; e < EA; ++e) ra[e] = pa[aoff[e] + kba];
 #pragma unroll
-      for (int e = 0; e < EB; ++e) rb[e] = (!FAN || pbe[e]) ? pbe[e][boff[e] + kbb] : f32x2{0.f, 0.f};
+      for (int e = 0; e < EB; ++e) rb[e] = pbe[e][boff[e] + kbb];
     };
     auto lstore = [&](int buf) {
 #pragma unroll
@@ -153,22 +166,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
     const float bsign = (half == 1 && dsel == 0) ? -1.f : 1.f;
     const int aplane = half ? APL : 0;
 
-    // output offsets of this lane (independent of k, fetched before the k
-    // loop): m of each row block, n of each accumulator register pair and,
-    // for fan tiles, the output instance of its slot
-    uint32_t om[RM], ocn[RN][8];
-    int32_t jgv[RN][8];
+    // output offsets of this lane's m values, fetched before the k loop
+    uint32_t om[RM];
 #pragma unroll
     for (int i = 0; i < RM; ++i) om[i] = tlook(tab + TAB_CM * kTabSize, m0 + (wm * RM + i) * 32 + l32);
-#pragma unroll
-    for (int q = 0; q < RN; ++q)
-#pragma unroll
-      for (int rr = 0; rr < 8; ++rr) {
-        const int row = 8 * (rr >> 1) + 4 * half + 2 * (rr & 1);
-        const uint32_t n = n0 + (wn * RN + q) * 16 + (row >> 1);
-        ocn[q][rr] = tlook(tab + TAB_CN * kTabSize, FAN ? (n & nmask) : n);
-        jgv[q][rr] = FAN ? fj[n >> d.nbits] : 0;
-      }
 
     // k offsets run one step ahead of the loads that use them, so that their
     // table reads are in flight during a whole step of MFMA work
@@ -212,18 +213,22 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
 #pragma unroll
       for (int rr = 0; rr < 8; ++rr) {
         const int r = 2 * rr;
+        const int row = 8 * (rr >> 1) + 4 * half + 2 * (rr & 1);
+        const int nl = (wn * RN + q) * 16 + (row >> 1);  // column within the tile
         gptr<f32x2> dst = pc;
         bool live = true;
         if (FAN) {
-          const int jg = jgv[q][rr];  // uniform over the 32 lanes of a half-wave (one n)
-          live = jg >= 0;
-          dst = gmem<f32x2>(ws + d.c_off + (s * d.w + (live ? jg : 0)) * d.c_inst_bytes);
+          const uint64_t cb = s_cb[nl >> d.nbits];  // uniform over the 32 lanes of a half-wave (one n)
+          live = cb != 0;
+          dst = gmem<f32x2>(ws + cb);
         }
+        const uint32_t ocn = s_cn[nl];
 #pragma unroll
         for (int i = 0; i < RM; ++i)
-          if (live) dst[om[i] + ocn[q][rr]] = f32x2{acc[i][q][r], acc[i][q][r + 1]};
+          if (live) dst[om[i] + ocn] = f32x2{acc[i][q][r], acc[i][q][r + 1]};
       }
     }
+    __syncthreads();  // the next tile rewrites the column data
   }
 }
 
