@@ -196,8 +196,10 @@ int matnc_plan_destroy(matnc_plan plan);
  * matnc_plan_autotune -- choose the tile configuration of every step that
  * runs on the MFMA kernel by timing each configuration that fits the step's
  * shape (reps launches each, HIP events on the bound stream) and keeping the
- * fastest; then re-capture the graph.  Choices are keyed by shape class
- * (precision, m/n/k bits, instance count rounded to a power of two) and, if
+ * fastest; for fan-out steps the configuration's N width (32 or 64 complex
+ * columns) also picks the fan table.  The launch graphs are re-captured at
+ * the next execute.  Choices are keyed by shape class (precision, storage,
+ * fan-out, m/n/k bits, instance count rounded to a power of two) and, if
  * cache_path is not NULL, read from and written back to that JSON file
  * (classes already in the file are not re-timed).  Overwrites intermediate
  * tensors (the stem cache is recomputed at the next execute).  Waits for the
