@@ -336,7 +336,7 @@ def main():
     t_tune = 0.0
     if not args.no_autotune:
         t0 = time.perf_counter()
-        run.autotune(reps=2)
+        run.autotune(reps=3)
         t_tune = time.perf_counter() - t0
     info = run.info
     log(f"plan {t_plan:.2f}s bind {t_bind:.2f}s autotune {t_tune:.2f}s workspace {info.workspace_bytes / 2**30:.2f} GiB "

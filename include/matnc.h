@@ -195,8 +195,8 @@ int matnc_plan_destroy(matnc_plan plan);
 /*
  * matnc_plan_autotune -- choose the tile configuration of every step that
  * runs on the MFMA kernel by timing each configuration that fits the step's
- * shape (reps launches each, HIP events on the bound stream) and keeping the
- * fastest; for fan-out steps the configuration's N width (32 or 64 complex
+ * shape (the fastest of reps separately timed launches, HIP events on the
+ * bound stream) and keeping the fastest configuration; for fan-out steps the configuration's N width (32 or 64 complex
  * columns) also picks the fan table.  The launch graphs are re-captured at
  * the next execute.  Choices are keyed by shape class (precision, storage,
  * fan-out, m/n/k bits, instance count rounded to a power of two) and, if

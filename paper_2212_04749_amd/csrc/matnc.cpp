@@ -1267,12 +1267,18 @@ int matnc_plan_autotune(matnc_plan plan, int reps, const char* cache_path) {
         use(c);
         const NodeDesc d0 = node_desc(P, v, V.dep ? P.batch : 1);
         launch_node(P, V, d0, st);  // warm-up
-        hip_check(hipEventRecord(e0, st), "event record");
-        for (int r = 0; r < reps; ++r) launch_node(P, V, d0, st);
-        hip_check(hipEventRecord(e1, st), "event record");
-        hip_check(hipEventSynchronize(e1), "event sync");
+        // the fastest of reps separately timed launches (robust to a slow
+        // outlier launch)
         float ms = 0.f;
-        hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
+        for (int r = 0; r < reps; ++r) {
+          hip_check(hipEventRecord(e0, st), "event record");
+          launch_node(P, V, d0, st);
+          hip_check(hipEventRecord(e1, st), "event record");
+          hip_check(hipEventSynchronize(e1), "event sync");
+          float t = 0.f;
+          hip_check(hipEventElapsedTime(&t, e0, e1), "event time");
+          ms = r == 0 ? t : std::min(ms, t);
+        }
         if (!have || ms < best) {
           have = true;
           best = ms;
