@@ -1,0 +1,36 @@
+"""bench.py's contract on the host: more than one GPU is refused with a
+message (this build runs on one GPU), and the recorded PMC traffic is only
+reported while the kernel sources it was taken with are unchanged."""
+
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in out["error"] and out["n_gpus"] == 2
+
+
+def test_traffic_record_needs_unchanged_sources(tmp_path, monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+    rec = {"workload": "CX", "precision": "c64", "kernel_id": 7, "bytes_per_launch": 123,
+           "sources": {"bench.py": "0" * 64}}
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "x.md").write_text("text\n<!-- traffic " + json.dumps(rec) + " -->\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "bench.py").write_text("changed")
+    assert bench.pmc_traffic("CX", "c64", 7) is None
+    import hashlib
+    rec["sources"] = {"bench.py": hashlib.sha256(b"changed").hexdigest()}
+    (prof / "x.md").write_text("<!-- traffic " + json.dumps(rec) + " -->\n")
+    assert bench.pmc_traffic("CX", "c64", 7) == 123.0
+    assert bench.pmc_traffic("CX", "c64", 8) is None
