@@ -51,6 +51,17 @@ __device__ __forceinline__ void max_scale_mx(uint64_t base, int64_t i, uint32_t 
   gmax_u32(base + (uint64_t)i * sizeof(HalfScale) + offsetof(HalfScale, mx), mx_bits);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  A grid-stride index vid (grid size a multiple of 8, or a single
+// pass) maps to a logical tile so that XCD x works through the contiguous
+// logical range [start(x), start(x) + count(x)): neighbouring tiles, which
+// share operand data, then meet in the same L2.  A bijection on [0, total).
+__device__ __forceinline__ int64_t xcd_tile(int64_t vid, int64_t total) {
+  const int64_t q = total >> 3, r = total & 7;
+  const int64_t x = vid & 7, k = vid >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
+
 template <typename P>
 __device__ __forceinline__ uint32_t tlook(P T, uint32_t x) {
   return T[x & 255u] + T[256 + ((x >> 8) & 255u)] + T[512 + ((x >> 16) & 255u)] + T[768 + (x >> 24)];

@@ -74,10 +74,13 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
   const int slots = FAN ? (TN >> d.nbits) : 1;
 
   for (int64_t blk = blockIdx.x; blk < units * tiles; blk += gridDim.x) {
-    const int64_t u = blk / tiles;
-    const int64_t t = blk - u * tiles;
-    const uint32_t m0 = (uint32_t)((t % mt_count) * TM);
-    const uint32_t n0 = (uint32_t)((t / mt_count) * TN);
+    // logical tile order: n tiles innermost (they share the A tile), then m
+    // tiles, then instances / fan rows; each XCD takes a contiguous range
+    const int64_t lt = xcd_tile(blk, units * tiles);
+    const int64_t u = lt / tiles;
+    const int64_t t = lt - u * tiles;
+    const uint32_t m0 = (uint32_t)((t / nt_count) * TM);
+    const uint32_t n0 = (uint32_t)((t % nt_count) * TN);
     int64_t s, j;
     gptr<const int32_t> fj = nullptr;
     if (FAN) {
