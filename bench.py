@@ -48,6 +48,9 @@ def parse():
     p.add_argument("--precision", default="c64", choices=["c64", "chalf"])
     p.add_argument("--slice-batch", type=int, default=0, help="0 = workload default")
     p.add_argument("--trials", type=int, default=32, help="order-search candidates")
+    p.add_argument("--partition-trials", type=int, default=-1,
+                   help="bisection candidates of the order search (-1: 16 for the 36- and 53-qubit "
+                        "workloads, none otherwise)")
     p.add_argument("--slice-subset", type=int, default=0, metavar="N",
                    help="time N consecutive slices (seeded start) instead of all of them and project the "
                         "full-job rate (the large workloads); 0 = every slice")
@@ -324,7 +327,8 @@ def main():
     cap = w.cap if w.cap is not None else 32
     # at least the workload's slice count; a cheaper plan that needs more
     # sliced indices to meet the rank cap keeps its real count
-    plan = planner.find_plan(net, words, w.open_qubits, w.cap, seed=0, trials=args.trials,
+    pt = args.partition_trials if args.partition_trials >= 0 else (16 if name in ("C3", "C4") else 0)
+    plan = planner.find_plan(net, words, w.open_qubits, w.cap, seed=0, trials=args.trials, partition_trials=pt,
                              min_slices=w.n_slices_target.bit_length() - 1 if w.n_slices_target else 0,
                              progress=lambda msg: log(f"planning: {msg}"))
     spec = api.PlanSpec(plan.pairs, plan.sliced, tuple(w.open_qubits), cap, plan.method)

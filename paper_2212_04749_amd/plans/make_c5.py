@@ -1,7 +1,8 @@
 """Writes c5_cap30.json: contraction trees and sliced sets of the 32 uneven
 circuits (workload.configs.uneven_batch_c5) at rank cap 30, found by the
-planner with the time objective (8 candidates, 2 refined).  Planning all 32
-takes about 25 minutes on one host core, so the uneven-batch runs load the
+planner with the time objective (8 greedy and 8 bisection candidates, 2
+refined).  Planning all 32 takes about an hour on one host core, so the
+uneven-batch runs load the
 stored plans; any tree is valid input to the library (the contraction tree
 is given, main text), and the file only saves the search.
 
@@ -28,9 +29,10 @@ def main() -> None:
     out = {}
     for w in uneven_batch_c5():
         net = build_network(w.circuit())
-        pl = planner.find_plan(net, w.bitstrings(), (), CAP, trials=8, objective="time", refine_top=2)
+        pl = planner.find_plan(net, w.bitstrings(), (), CAP, trials=8, partition_trials=8, objective="time",
+                               refine_top=2)
         out[w.name] = {"pairs": [list(p) for p in pl.pairs], "sliced": list(pl.sliced), "cap": CAP,
-                       "method": pl.method, "est_seconds": pl.costs.time, "cmac_total": pl.costs.total}
+                       "est_seconds": pl.costs.time, "cmac_total": pl.costs.total}
         print(w.name, len(pl.sliced), f"{pl.costs.time:.2f}s", flush=True)
     with open(PATH, "w") as f:
         json.dump(out, f, separators=(",", ":"))
