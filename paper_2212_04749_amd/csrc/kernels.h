@@ -16,6 +16,9 @@ hipError_t launch_mfma(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* s
 // fan-out tiles (d.fan_off / d.n_fan describe the grouping)
 bool mfma_fan_config_fits(int cfg, int mbits, int nbits, int kbits, int fan_tn);
 hipError_t launch_mfma_fan(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st);
+// the same, also recording each output instance's maximum (its scale slot
+// must have been cleared)
+hipError_t launch_mfma_fan_rec(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st);
 // adds the root instances of slices sigma0 .. sigma0+nb-1 into rows[0..nrows)
 // of amps (root.gmap_off: local root instance of each row position)
 hipError_t launch_slice_sum(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t nrows,

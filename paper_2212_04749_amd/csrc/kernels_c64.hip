@@ -34,8 +34,13 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // FAN: the tile's TN columns are TN >> nbits slots of 2^nbits columns, one
 // per output instance of a fan-table row (see NodeDesc); the A tile is
 // loaded once for all of them.
-template <int RM, int RN, int WM, int WN, int TK, bool FAN>
+// REC (fan tiles only): also record each output instance's largest
+// |component| into its scale slot (complex-half plans, whose FP32 branch
+// tensors feed FP16 steps): half-wave reductions and one LDS atomic per
+// slot column, one global atomic per slot and tile.
+template <int RM, int RN, int WM, int WN, int TK, bool FAN, bool REC = false>
 __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
+  static_assert(!REC || FAN, "maxima are recorded by fan-out tiles only");
   constexpr int NT = 64 * WM * WN;
   constexpr int TM = 32 * RM * WM;
   constexpr int TN = 16 * RN * WN;
@@ -52,6 +57,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
   __shared__ uint32_t s_cn[TN];
   __shared__ uint64_t s_bb[FAN ? TN : 1];
   __shared__ uint64_t s_cb[FAN ? TN : 1];
+  __shared__ uint32_t s_mx[REC ? TN : 1];  // per-slot maxima (float bits)
 
   const gptr<const uint32_t> tab = gmem<const uint32_t>(ws + d.tab_off);
   const gptr<const int32_t> glA = gmem<const int32_t>(ws + d.A.gmap_off);
@@ -104,6 +110,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
       const int jg = fj[tid];
       s_bb[tid] = d.B.off + operand_instance(d.B, glB, jg < 0 ? j : jg, s, sigma) * d.B.inst_bytes;
       s_cb[tid] = jg < 0 ? 0 : d.c_off + (uint64_t)(s * d.w + jg) * d.c_inst_bytes;
+      if (REC) s_mx[tid] = 0u;
     }
     __syncthreads();  // the column data above is read by every wave
 
@@ -226,9 +233,25 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
           dst = gmem<f32x2>(ws + cb);
         }
         const uint32_t ocn = s_cn[nl];
+        float v = 0.f;
 #pragma unroll
-        for (int i = 0; i < RM; ++i)
+        for (int i = 0; i < RM; ++i) {
           if (live) dst[om[i] + ocn] = f32x2{acc[i][q][r], acc[i][q][r + 1]};
+          if (REC) v = fmaxf(v, fmaxf(fabsf(acc[i][q][r]), fabsf(acc[i][q][r + 1])));
+        }
+        if (REC) {
+          // the half-wave's 32 lanes hold 32 values of m of one column
+#pragma unroll
+          for (int o = 16; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+          if (l32 == 0 && live) atomicMax(&s_mx[nl >> d.nbits], __float_as_uint(v));
+        }
+      }
+    }
+    if (REC) {
+      __syncthreads();
+      if (tid < slots) {
+        const int jg = fj[tid];
+        if (jg >= 0 && s_mx[tid] > 0u) max_scale_mx(ws + d.c_scale_off, s * d.w + jg, s_mx[tid]);
       }
     }
     __syncthreads();  // the next tile rewrites the column data
@@ -313,7 +336,7 @@ bool mfma_fan_config_fits(int cfg, int mbits, int nbits, int kbits, int fan_tn) 
   return (1 << c.tn_bits) == fan_tn && nbits < c.tn_bits && mbits >= c.tm_bits && kbits >= c.tk_bits;
 }
 
-template <bool FAN>
+template <bool FAN, bool REC = false>
 static hipError_t launch_mfma_t(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
   if (d.n_inst == 0) return hipSuccess;
   const bool fits = FAN ? mfma_fan_config_fits(cfg, d.mbits, d.nbits, d.kbits, d.fan_tn)
@@ -324,14 +347,14 @@ static hipError_t launch_mfma_t(const NodeDesc& d, int cfg, uint64_t ws, const i
   const int64_t tiles = ((int64_t)1 << (d.mbits - c.tm_bits)) * (FAN ? 1 : ((int64_t)1 << (d.nbits - c.tn_bits)));
   const unsigned grid = grid_for(units * tiles);
   switch (cfg) {
-    case 0: hipLaunchKernelGGL((k_mfma<2, 1, 2, 2, 8, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 1: hipLaunchKernelGGL((k_mfma<2, 2, 2, 2, 8, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 2: hipLaunchKernelGGL((k_mfma<1, 1, 2, 2, 8, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 3: hipLaunchKernelGGL((k_mfma<4, 1, 2, 2, 8, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 4: hipLaunchKernelGGL((k_mfma<4, 2, 2, 2, 8, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 0: hipLaunchKernelGGL((k_mfma<2, 1, 2, 2, 8, FAN, REC>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 1: hipLaunchKernelGGL((k_mfma<2, 2, 2, 2, 8, FAN, REC>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 2: hipLaunchKernelGGL((k_mfma<1, 1, 2, 2, 8, FAN, REC>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 3: hipLaunchKernelGGL((k_mfma<4, 1, 2, 2, 8, FAN, REC>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 4: hipLaunchKernelGGL((k_mfma<4, 2, 2, 2, 8, FAN, REC>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
     case 5:
       if (FAN) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((k_mfma<2, 4, 2, 2, 8, false>), dim3(grid), dim3(256), 0, st, d, ws, sig);
+      hipLaunchKernelGGL((k_mfma<2, 4, 2, 2, 8, false, false>), dim3(grid), dim3(256), 0, st, d, ws, sig);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -344,6 +367,10 @@ hipError_t launch_mfma(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* s
 
 hipError_t launch_mfma_fan(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
   return launch_mfma_t<true>(d, cfg, ws, sig, st);
+}
+
+hipError_t launch_mfma_fan_rec(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
+  return launch_mfma_t<true, true>(d, cfg, ws, sig, st);
 }
 
 hipError_t launch_slice_sum(const OpDesc& root, uint64_t ws, const int64_t* sig, int nb, int64_t nrows,

@@ -769,11 +769,16 @@ void launch_node(const Plan& P, const PNode& V, const NodeDesc& d, hipStream_t s
   const int64_t* sig = reinterpret_cast<const int64_t*>(P.ws + P.sigma_off);
   hipError_t e;
   if (V.kernel == 1 && !V.half_store) {
-    // FP32 MFMA; an FP16 consumer's scaling needs the output maxima, which
-    // a separate reduction pass records (cheaper than doing it in the GEMM
-    // epilogue, whose register use would cut the occupancy)
-    e = V.fan ? launch_mfma_fan(d, V.cfg, P.ws, sig, st) : launch_mfma(d, V.cfg, P.ws, sig, st);
-    if (e == hipSuccess && V.rec_max) e = launch_absmax(d, P.ws, st);
+    // FP32 MFMA; an FP16 consumer's scaling needs the output maxima: fan-out
+    // tiles record them in their epilogue, other tiles leave them to a
+    // separate reduction pass (recording in the epilogue of the big tiles
+    // raises their register use and cuts the occupancy)
+    if (V.fan) {
+      e = V.rec_max ? launch_mfma_fan_rec(d, V.cfg, P.ws, sig, st) : launch_mfma_fan(d, V.cfg, P.ws, sig, st);
+    } else {
+      e = launch_mfma(d, V.cfg, P.ws, sig, st);
+      if (e == hipSuccess && V.rec_max) e = launch_absmax(d, P.ws, st);
+    }
   } else if (V.kernel == 1) {
     e = V.fan ? launch_mfma_h_fan(d, V.cfg, P.ws, sig, st) : launch_mfma_h(d, V.cfg, P.ws, sig, st);
   } else if (P.precision == MATNC_C64) {
