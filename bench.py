@@ -43,7 +43,7 @@ def parse():
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4", "C5"])
-    p.add_argument("--max-est-s", type=float, default=20.0,
+    p.add_argument("--max-est-s", type=float, default=100.0,
                    help="uneven batch (C5): leave out circuits whose plan's estimated time exceeds this")
     p.add_argument("--precision", default="c64", choices=["c64", "chalf"])
     p.add_argument("--slice-batch", type=int, default=0, help="0 = workload default")
