@@ -29,7 +29,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"c64": 157.3, "chalf": 2516.6}  # dense MFMA: FP32, FP16
+PEAK_TFLOPS = {"fp32": 157.3, "fp16": 2516.6}  # dense MFMA
 PEAK_HBM_GBS = 8000.0
 
 
@@ -139,16 +139,20 @@ def roofline(run, precision, n_batches, nb_last, workload):
     e = per[kid]
     t = e["ms"] / 1e3
     if kid >= 100:
+        # 100/200 + c: FP32 MFMA (complex64, and the FP32 steps of
+        # complex-half); 300/400 + c: FP16 MFMA
         achieved = 8 * e["cmac"] / t / 1e12
-        r = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s"}
+        r = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["fp16" if kid >= 300 else "fp32"],
+             "unit": "TFLOP/s"}
     else:
         achieved = e["bytes"] / t / 1e9
         r = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     r["frac"] = r["achieved"] / r["peak"]
     r["traffic"] = pmc_traffic(workload, precision, kid)
     r["algorithmic_bytes_per_launch"] = e["bytes"] / e["launches"]
-    r["kernel"] = (f"mfma fan-out cfg {kid - 200}" if kid >= 200 else
-                   f"mfma cfg {kid - 100}" if kid >= 100 else "streaming")
+    r["kernel"] = ("streaming" if kid < 100 else
+                   f"{'fp16' if kid >= 300 else 'fp32'} mfma{' fan-out' if (kid // 100) % 2 == 0 else ''} "
+                   f"cfg {kid % 100}")
     r["launches"] = e["launches"]
     r["mean_launch_ms"] = e["ms"] / e["launches"]
     r["share_of_step"] = e["ms"] / sum(v["ms"] for v in per.values())
@@ -202,6 +206,9 @@ def cpu_baseline(name, w):
                       f"{t_full:.1f} s for all {w.k} bitstrings"}
 
 
+GROUP_EST_S = 30.0
+
+
 def run_uneven(args) -> None:
     """The uneven batch: the 32 seeded circuits of workload.configs with the
     stored plans (plans/c5_cap30.json), in complex-half by default. Plans
@@ -237,15 +244,20 @@ def run_uneven(args) -> None:
         B.matnc_network_destroy(h)
         items.append((need, w, e, net))
     items.sort(key=lambda x: -x[0])
+    # first fit, largest workspace first; a group also stays under about
+    # GROUP_EST_S of estimated work so that each pass over it reports back
+    # within a bounded time (a single larger plan gets a group of its own)
     groups = []
-    for it in items:  # first fit, largest first
+    for it in items:
+        est = it[2]["est_seconds"]
         for g in groups:
-            if g["bytes"] + it[0] <= cap_bytes:
+            if g["bytes"] + it[0] <= cap_bytes and g["est"] + est <= GROUP_EST_S:
                 g["items"].append(it)
                 g["bytes"] += it[0]
+                g["est"] += est
                 break
         else:
-            groups.append({"bytes": it[0], "items": [it]})
+            groups.append({"bytes": it[0], "est": est, "items": [it]})
     log(f"uneven batch: {len(sel)} circuits in {len(groups)} queue groups, {len(skipped)} left out "
         f"(estimated over {args.max_est_s} s each)")
     total_ms = 0.0
@@ -258,10 +270,15 @@ def run_uneven(args) -> None:
             runs.append(api.Contraction(net, spec, w.bitstrings(), precision=prec, slice_batch=1, stream=stream,
                                         memory_budget=need))
         q = api.Queue(runs)
+        log(f"group {gi}: {len(runs)} circuits ({', '.join(it[1].name for it in g['items'])}), "
+            f"estimated {g['est']:.1f} s per pass; capturing")
+        t0 = time.perf_counter()
         amps, xeb = q.execute()  # capture
+        stream.synchronize()
+        log(f"group {gi}: first pass {time.perf_counter() - t0:.1f} s")
         for _ in range(args.warmup):
             q.execute(amps, xeb)
-        stream.synchronize()
+            stream.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
         for _ in range(args.steps):
@@ -434,7 +451,10 @@ def main():
         "dtype": "complex64" if args.precision == "c64" else "complex-half",
         "data": "synthetic",
         "complex_tflops": 8 * cmac_timed / (ms_step / 1e3) / 1e12,
-        "mfma_peak_frac": 8 * cmac_timed / (ms_step / 1e3) / 1e12 / PEAK_TFLOPS[args.precision],
+        # whole-step rate over the FP32 MFMA peak (complex64 runs all its
+        # GEMM steps on FP32 MFMA; complex-half mixes FP32 and FP16 steps)
+        "mfma_peak_frac": (8 * cmac_timed / (ms_step / 1e3) / 1e12 / PEAK_TFLOPS["fp32"]
+                           if args.precision == "c64" else None),
         "xeb": xeb,
         "error_vs_fp64": err,
         "plan_s": t_plan,

@@ -221,9 +221,12 @@ int matnc_plan_reset_cache(matnc_plan plan);
  * on the bound stream; waits for the stream.  For step j (0 <= j <
  * n_tensors - 1) it writes
  *   time_ms[j]  elapsed time of that launch (-1 if the node has no work),
- *   kernel[j]   0 = streaming kernel, 100 + c = MFMA tile configuration c,
- *               200 + c = MFMA configuration c as fan-out tiles (the output
- *               instances that share an A instance computed as one GEMM),
+ *   kernel[j]   0 = streaming kernel, 100 + c = FP32 MFMA tile
+ *               configuration c, 200 + c = FP32 MFMA configuration c as
+ *               fan-out tiles (the output instances that share an A
+ *               instance computed as one GEMM); 300 + c and 400 + c the
+ *               same for the FP16 MFMA kernels of complex-half steps whose
+ *               result is stored in FP16,
  *   cmac[j]     algorithmic complex MACs of the launch (w * instances * 2^(m+n+k)),
  *   bytes[j]    algorithmic HBM bytes of the launch (each output instance
  *               written once, each distinct operand instance read once).

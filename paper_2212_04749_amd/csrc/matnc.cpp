@@ -1359,7 +1359,7 @@ int matnc_plan_profile(matnc_plan plan, int64_t slice_begin, int nb, float* time
       float ms = 0.f;
       hip_check(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]), "event time");
       time_ms[j] = ms;
-      kernel[j] = V.kernel == 1 ? (V.fan ? 200 : 100) + V.cfg : 0;
+      kernel[j] = V.kernel == 1 ? (V.half_store ? 300 : 100) + (V.fan ? 100 : 0) + V.cfg : 0;
       const NodeDesc d = node_desc(P, v, V.dep ? nb : 1);
       const double inst = (double)d.n_inst;
       cmac[j] = inst * std::ldexp(1.0, (int)(V.M.size() + V.N.size() + V.K.size()));

@@ -29,7 +29,10 @@ id pair) is also available and is one of the candidates.
 Slicer: while some tensor is over the cap, slice the index that most
 reduces the total rank overflow above the cap (sum over tensors of
 rank - cap), then the one with the lowest total cost (slice-invariant nodes
-once, the rest times 2^|S|), ties to the lowest index id.
+once, the rest times 2^|S|), ties to the lowest index id.  The rank cap
+bounds one instance; a multi-amplitude tensor holds w(v) of them, so an
+optional second cap bounds log2(w(v) 2^|v|), the elements the device holds
+for node v, and counts in the overflow the same way.
 
 Objective.  ``objective="flops"`` scores plans by the paper's loss: the
 complex MACs over all slices.  ``objective="time"`` (the default) scores
@@ -403,30 +406,46 @@ def timeline_pairs(st: Structure, k_eff: int, rng=None) -> List[Tuple[int, int]]
     return pairs
 
 
+def _overflow(masks: Sequence[int], lw: Sequence[float], cap: Optional[int], mem_cap: Optional[float]) -> float:
+    """Sum over tensors of the rank above ``cap`` plus log2(w(v) 2^|v|)
+    above ``mem_cap`` (lw: log2 w per node)."""
+    over = 0.0
+    for m, l in zip(masks, lw):
+        r = m.bit_count()
+        if cap is not None and r > cap:
+            over += r - cap
+        if mem_cap is not None and r + l > mem_cap + 1e-9:
+            over += r + l - mem_cap
+    return over
+
+
 def slice_to_cap(st: Structure, pairs: Sequence[Tuple[int, int]], w: Sequence[int],
                  cap: Optional[int], min_slices: int = 0,
-                 max_sliced: int = 40, objective: str = "time") -> Tuple[List[int], Costs]:
-    """Slicer: while max rank > cap (or fewer than min_slices indices are
-    sliced), add the index that most reduces the rank overflow above the
-    cap, then minimises the total cost, ties to the lowest id.  Open output
-    indices are never sliced."""
+                 max_sliced: int = 40, objective: str = "time",
+                 mem_cap: Optional[float] = None) -> Tuple[List[int], Costs]:
+    """Slicer: while some tensor is over the rank cap or its multi-amplitude
+    form (w(v) instances of 2^|v| elements) is over 2^mem_cap elements (or
+    fewer than min_slices indices are sliced), add the index that most
+    reduces the overflow above the caps, then minimises the total cost, ties
+    to the lowest id.  Open output indices are never sliced."""
     sliced_mask = 0
     chosen: List[int] = []
+    lw = [math.log2(max(x, 1)) for x in w]
     tree = build_tree(st, pairs, 0)
     while True:
         tree = build_tree(st, pairs, sliced_mask)
-        mr = max(m.bit_count() for m in tree.masks)
-        if (cap is None or mr <= cap) and len(chosen) >= min_slices:
+        over_now = _overflow(tree.masks, lw, cap, mem_cap)
+        if over_now == 0.0 and len(chosen) >= min_slices:
             return chosen, costs(st, tree, w, sliced_mask)
         if len(chosen) >= max_sliced:
             raise ValueError("slicer: too many sliced indices for the cap")
-        if cap is not None and mr > cap:
-            cand = 0
-            for m in tree.masks:
-                if m.bit_count() > cap:
+        cand = 0
+        if over_now > 0.0:
+            for m, l in zip(tree.masks, lw):
+                r = m.bit_count()
+                if (cap is not None and r > cap) or (mem_cap is not None and r + l > mem_cap + 1e-9):
                     cand |= m
         else:
-            cand = 0
             for m in tree.masks:
                 cand |= m
         cand &= ~st.open_indices
@@ -435,8 +454,8 @@ def slice_to_cap(st: Structure, pairs: Sequence[Tuple[int, int]], w: Sequence[in
             trial_mask = sliced_mask | (1 << i)
             t2 = build_tree(st, pairs, trial_mask)
             c = costs(st, t2, w, trial_mask)
-            # first shrink the total rank overflow above the cap, then cost
-            over = 0 if cap is None else sum(max(0, m.bit_count() - cap) for m in t2.masks)
+            # first shrink the total overflow above the caps, then cost
+            over = _overflow(t2.masks, lw, cap, mem_cap)
             key = (over, c.score(objective), i)
             if best is None or key < best[0]:
                 best = (key, i)
@@ -457,7 +476,7 @@ class Plan:
 
 def refine(st: Structure, plan: Plan, words: np.ndarray, cap: Optional[int],
            exact_slices: Optional[int] = None, rounds: int = 4, objective: str = "time",
-           min_slices: int = 0) -> Plan:
+           min_slices: int = 0, mem_cap: Optional[float] = None) -> Plan:
     """Alternate subtree reconfiguration (sizes 6, 8, 10) with re-slicing
     until the objective stops falling."""
     best = plan
@@ -466,13 +485,15 @@ def refine(st: Structure, plan: Plan, words: np.ndarray, cap: Optional[int],
     for _ in range(rounds):
         sl = sum(1 << i for i in sliced)
         for size in (6, 8, 10):
-            pairs = reconfigure(st, pairs, words, cap, sl, size=size, passes=4, objective=objective)
+            pairs = reconfigure(st, pairs, words, cap, sl, size=size, passes=4, objective=objective,
+                                mem_cap=mem_cap)
         tree = build_tree(st, pairs)
         w = widths(tree, words)
         c = costs(st, build_tree(st, pairs, sl), w, sl)
         cand = Plan(pairs, sliced, c, w, best.method + "+reconf")
         try:
-            s2, c2 = slice_to_cap(st, pairs, w, cap, min_slices=exact_slices or min_slices, objective=objective)
+            s2, c2 = slice_to_cap(st, pairs, w, cap, min_slices=exact_slices or min_slices, objective=objective,
+                                  mem_cap=mem_cap)
             if (exact_slices is None or len(s2) == exact_slices) and c2.score(objective) < c.score(objective):
                 cand = Plan(pairs, s2, c2, w, best.method + "+reconf")
         except ValueError:
@@ -490,10 +511,11 @@ def find_plan(net: TensorNetwork, words: np.ndarray, open_qubits: Sequence[int] 
               min_slices: int = 0, exact_slices: Optional[int] = None,
               include_greedy: bool = True, refine_top: int = 3, partition_trials: int = 0,
               rgreedy_trials: int = 0, timeline: bool = False, max_sliced: int = 40,
-              objective: str = "time", progress=None) -> Plan:
+              objective: str = "time", progress=None, mem_cap: Optional[float] = None) -> Plan:
     """Search candidate orders; slice each to the cap; refine the cheapest
     few by subtree reconfiguration; keep the cheapest under ``objective``
-    ("time" or "flops", see the module docstring)."""
+    ("time" or "flops", see the module docstring).  ``mem_cap`` bounds
+    log2 of the elements of every multi-amplitude tensor, w(v) 2^|v|."""
     if objective not in ("time", "flops"):
         raise ValueError("objective must be 'time' or 'flops'")
     st = Structure.from_network(net, open_qubits)
@@ -526,7 +548,7 @@ def find_plan(net: TensorNetwork, words: np.ndarray, open_qubits: Sequence[int] 
         w = widths(tree, words)
         try:
             sliced, c = slice_to_cap(st, pairs, w, cap, min_slices=(exact_slices or min_slices),
-                                     max_sliced=max_sliced, objective=objective)
+                                     max_sliced=max_sliced, objective=objective, mem_cap=mem_cap)
         except ValueError:
             continue
         # an exact slice count (C3's 2^8) is preferred; a plan that needs more
@@ -545,9 +567,11 @@ def find_plan(net: TensorNetwork, words: np.ndarray, open_qubits: Sequence[int] 
         if refine_top > 0:
             # the flop objective's local search first (it escapes the poor
             # initial shapes best), then the time objective from there
-            r = refine(st, pl, words, cap, exact_slices, objective="flops", min_slices=min_slices)
+            r = refine(st, pl, words, cap, exact_slices, objective="flops", min_slices=min_slices,
+                       mem_cap=mem_cap)
             if objective == "time":
-                r = refine(st, r, words, cap, exact_slices, objective="time", min_slices=min_slices)
+                r = refine(st, r, words, cap, exact_slices, objective="time", min_slices=min_slices,
+                           mem_cap=mem_cap)
         miss = 0 if exact_slices is None else abs(len(r.sliced) - exact_slices)
         out.append(((miss, r.costs.score(objective), r.costs.max_rank), r))
     out.sort(key=lambda x: x[0])
@@ -633,7 +657,7 @@ def _node_cost(T: _Tree, objective: str, my: int, mz: int, oy: int, oz: int, w: 
     return step_time(w, wa, wb, ra, rb, (my ^ mz).bit_count(), (my & mz).bit_count())
 
 
-def _optimal_subtree(T: _Tree, frontier, cap, objective: str = "flops"):
+def _optimal_subtree(T: _Tree, frontier, cap, objective: str = "flops", mem_cap: Optional[float] = None):
     m = len(frontier)
     full = (1 << m) - 1
     fm = [T.masks[f] for f in frontier]
@@ -661,6 +685,8 @@ def _optimal_subtree(T: _Tree, frontier, cap, objective: str = "flops"):
         if cap is not None and bin(mask[s]).count("1") > cap:
             continue
         w = T.width(outs[s])
+        if mem_cap is not None and s != full and bin(mask[s]).count("1") + math.log2(w) > mem_cap + 1e-9:
+            continue
         f = mult if dep[s] else 1.0
         # enumerate splits with the lowest set bit in y to halve the work
         low = s & -s
@@ -690,7 +716,8 @@ def _subtree_cost(T: _Tree, v, frontier_set, objective: str = "flops"):
 
 
 def reconfigure(st: Structure, pairs, words, cap: Optional[int], sliced_mask: int = 0,
-                size: int = 8, passes: int = 2, objective: str = "flops") -> List[Tuple[int, int]]:
+                size: int = 8, passes: int = 2, objective: str = "flops",
+                mem_cap: Optional[float] = None) -> List[Tuple[int, int]]:
     """Local search over subtrees of ``size`` frontier nodes (see above)."""
     words = np.asarray(words, dtype=np.uint64)
     T = _Tree(st, pairs, sliced_mask, words)
@@ -719,7 +746,7 @@ def reconfigure(st: Structure, pairs, words, cap: Optional[int], sliced_mask: in
             if len(frontier) < 3:
                 continue
             old = _subtree_cost(T, v, set(frontier), objective)
-            new, split = _optimal_subtree(T, frontier, cap, objective)
+            new, split = _optimal_subtree(T, frontier, cap, objective, mem_cap)
             if new < old * (1 - 1e-9):
                 def build(s):
                     if s & (s - 1) == 0:

@@ -1,12 +1,14 @@
 """Writes c5_cap30.json: contraction trees and sliced sets of the 32 uneven
-circuits (workload.configs.uneven_batch_c5) at rank cap 30, found by the
-planner with the time objective (8 greedy and 8 bisection candidates, 2
-refined).  Planning all 32 takes about an hour on one host core, so the
-uneven-batch runs load the
-stored plans; any tree is valid input to the library (the contraction tree
-is given, main text), and the file only saves the search.
+circuits (workload.configs.uneven_batch_c5) at rank cap 30 and at most 2^33
+elements per multi-amplitude tensor (64 GiB in complex64, so that a plan's
+live tensors fit one device without splitting its keys into chunks), found
+by the planner with the time objective (8 greedy and 8 bisection candidates,
+2 refined).  Planning all 32 takes about an hour of host core time (spread
+over a process pool), so the uneven-batch runs load the stored plans; any
+tree is valid input to the library (the contraction tree is given, main
+text), and the file only saves the search.
 
-    python -m paper_2212_04749_amd.plans.make_c5
+    python -m paper_2212_04749_amd.plans.make_c5 [--jobs N]
 """
 
 from __future__ import annotations
@@ -18,24 +20,38 @@ from ..circuit_tn import build_network
 from .. import planner
 
 CAP = 30
+MEM_CAP = 33
 HERE = os.path.dirname(os.path.abspath(__file__))
 PATH = os.path.join(HERE, f"c5_cap{CAP}.json")
 
 
+def _plan_one(name: str):
+    from workload.configs import uneven_batch_c5
+    w = [x for x in uneven_batch_c5() if x.name == name][0]
+    net = build_network(w.circuit())
+    pl = planner.find_plan(net, w.bitstrings(), (), CAP, trials=8, partition_trials=8, objective="time",
+                           refine_top=2, mem_cap=MEM_CAP)
+    return name, {"pairs": [list(p) for p in pl.pairs], "sliced": list(pl.sliced), "cap": CAP,
+                  "mem_cap": MEM_CAP, "est_seconds": pl.costs.time, "cmac_total": pl.costs.total}
+
+
 def main() -> None:
+    import argparse
     import sys
+    from multiprocessing import Pool
     sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
     from workload.configs import uneven_batch_c5
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=max(1, min(8, os.cpu_count() or 1)))
+    args = ap.parse_args()
+    names = [w.name for w in uneven_batch_c5()]
     out = {}
-    for w in uneven_batch_c5():
-        net = build_network(w.circuit())
-        pl = planner.find_plan(net, w.bitstrings(), (), CAP, trials=8, partition_trials=8, objective="time",
-                               refine_top=2)
-        out[w.name] = {"pairs": [list(p) for p in pl.pairs], "sliced": list(pl.sliced), "cap": CAP,
-                       "est_seconds": pl.costs.time, "cmac_total": pl.costs.total}
-        print(w.name, len(pl.sliced), f"{pl.costs.time:.2f}s", flush=True)
+    with Pool(args.jobs) as pool:
+        for name, e in pool.imap_unordered(_plan_one, names):
+            out[name] = e
+            print(name, len(e["sliced"]), f"{e['est_seconds']:.2f}s", flush=True)
     with open(PATH, "w") as f:
-        json.dump(out, f, separators=(",", ":"))
+        json.dump({n: out[n] for n in names}, f, separators=(",", ":"))
 
 
 def load() -> dict:

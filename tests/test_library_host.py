@@ -168,3 +168,23 @@ def test_memory_budget_splits_keys_into_chunks():
     for p in (p1, p2):
         B.matnc_plan_destroy(p)
     B.matnc_network_destroy(h)
+
+
+def test_memory_cap_bounds_multi_amplitude_tensors():
+    # the rank cap bounds one instance of a tensor; the memory cap bounds the
+    # w(v) instances the device holds for node v
+    circ = random_circuit(GridSpec(3, 4), 8, 5)
+    words = uniform_bitstrings(12, 200, 6)
+    net = build_network(circ)
+    st = P.Structure.from_network(net, ())
+
+    def biggest(pl):
+        tree = P.build_tree(st, pl.pairs, sum(1 << i for i in pl.sliced))
+        w = P.widths(tree, words)
+        return max(math.log2(w[v]) + tree.masks[v].bit_count() for v in range(len(tree.masks)))
+
+    free = P.find_plan(net, words, (), None, trials=4)
+    assert biggest(free) > 10
+    capped = P.find_plan(net, words, (), None, trials=4, mem_cap=10)
+    assert biggest(capped) <= 10 + 1e-9
+    assert len(capped.sliced) >= 1
