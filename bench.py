@@ -209,6 +209,41 @@ def cpu_baseline(name, w):
 GROUP_EST_S = 30.0
 
 
+def run_in_parts(api, w, e, net, prec, need, stream, args, gi):
+    """One plan too large for a bounded queue pass: its slices run in
+    parts of about GROUP_EST_S estimated seconds, each timed with HIP events
+    and reported when it ends; the pass starts from an empty stem cache, so
+    the parts add up to one complete contraction."""
+    import math
+    import torch
+    spec = api.PlanSpec([tuple(x) for x in e["pairs"]], e["sliced"], (), e["cap"])
+    r = api.Contraction(net, spec, w.bitstrings(), precision=prec, slice_batch=1, stream=stream,
+                        memory_budget=need)
+    n = r.n_slices
+    parts = min(n, max(1, math.ceil(e["est_seconds"] / GROUP_EST_S)))
+    bounds = [n * i // parts for i in range(parts + 1)]
+    log(f"group {gi}: {w.name} alone, estimated {e['est_seconds']:.1f} s per pass, {n} slices in {parts} parts")
+    amps = None
+    for rep in range(args.warmup + args.steps):
+        timed = rep >= args.warmup
+        r.reset_cache()
+        amps = r.new_amplitudes() if amps is None else amps.zero_()
+        ms = 0.0
+        for i in range(parts):
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            r.execute(amps, bounds[i], bounds[i + 1])
+            ev1.record(stream)
+            stream.synchronize()
+            ms += ev0.elapsed_time(ev1)
+            log(f"group {gi}: {'timed' if timed else 'warm-up'} pass {rep}, slices [{bounds[i]}, {bounds[i + 1]}) "
+                f"done, {ms / 1e3:.1f} s so far")
+    x = r.xeb(amps)
+    out = (ms, x, r.k, r.info.cmac_total)
+    r.close()
+    return out
+
+
 def run_uneven(args) -> None:
     """The uneven batch: the 32 seeded circuits of workload.configs with the
     stored plans (plans/c5_cap30.json), in complex-half by default. Plans
@@ -264,6 +299,15 @@ def run_uneven(args) -> None:
     xebs, n_amps, cmac = {}, 0, 0.0
     stream = torch.cuda.Stream()
     for gi, g in enumerate(groups):
+        if len(g["items"]) == 1 and g["est"] > GROUP_EST_S:
+            need, w, e, net = g["items"][0]
+            ms, x, k, cm = run_in_parts(api, w, e, net, prec, need, stream, args, gi)
+            total_ms += ms
+            xebs[w.name] = x
+            n_amps += k
+            cmac += cm
+            torch.cuda.empty_cache()
+            continue
         runs = []
         for need, w, e, net in g["items"]:
             spec = api.PlanSpec([tuple(x) for x in e["pairs"]], e["sliced"], (), e["cap"])
