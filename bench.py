@@ -70,10 +70,17 @@ def copy_probe(mib: int) -> None:
     src = torch.ones(n, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
+    ms = []
     for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         dst.copy_(src)
-    torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 5}))
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    best = min(ms)
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 5,
+                      "best_ms": best, "copy_gbs": 2 * n * 4 / (best / 1e3) / 1e9}))
 
 
 def workload_description(name, w, info, spec):
@@ -115,10 +122,12 @@ def reference_error(name, run, amps_np):
     else:
         return None
     err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    max_over_rms = float(np.max(np.abs(got - ref)) / np.sqrt(np.mean(np.abs(ref) ** 2)))
     n = run.net.n_qubits
     xeb_gpu = float(np.ldexp(np.mean(np.abs(got) ** 2), n) - 1)
     xeb_ref = float(np.ldexp(np.mean(np.abs(ref) ** 2), n) - 1)
-    return {"rel_err": err, "samples": int(len(ref)), "xeb_abs_err_on_samples": abs(xeb_gpu - xeb_ref)}
+    return {"rel_err": err, "max_abs_err_over_rms": max_over_rms, "samples": int(len(ref)),
+            "xeb_abs_err_on_samples": abs(xeb_gpu - xeb_ref)}
 
 
 def roofline(run, precision, n_batches, nb_last, workload):
@@ -126,10 +135,13 @@ def roofline(run, precision, n_batches, nb_last, workload):
     flops (MFMA) or bytes (streaming) per launch over its mean launch time."""
     prof = run.profile(0, min(run.slice_batch, run.n_slices))
     per = {}
+    t_roof = 0.0  # sum over steps of max(flops / MFMA peak, bytes / HBM peak), ms
     for (ms, kid, cmac, by), dep in zip(prof, run.step_dep()):
         if ms < 0:
             continue
         reps = n_batches if dep else 1
+        peak = PEAK_TFLOPS["fp16" if kid >= 300 else "fp32"]
+        t_roof += reps * max(8 * cmac / (peak * 1e12), by / (PEAK_HBM_GBS * 1e9)) * 1e3
         e = per.setdefault(kid, {"ms": 0.0, "cmac": 0.0, "bytes": 0.0, "launches": 0})
         e["ms"] += ms * reps
         e["cmac"] += cmac * reps
@@ -156,7 +168,7 @@ def roofline(run, precision, n_batches, nb_last, workload):
     r["launches"] = e["launches"]
     r["mean_launch_ms"] = e["ms"] / e["launches"]
     r["share_of_step"] = e["ms"] / sum(v["ms"] for v in per.values())
-    return r, per
+    return r, per, t_roof
 
 
 def pmc_traffic(workload: str, precision: str, kernel_id: int):
@@ -448,7 +460,7 @@ def main():
     xeb = float(xeb_out.cpu().item()) if full else None
     err = reference_error(name, run, amps_c) if full else None
     n_batches = -(-run.n_slices // batch)
-    roof, per = roofline(run, args.precision, n_batches, run.n_slices - (n_batches - 1) * batch, name)
+    roof, per, t_roof_ms = roofline(run, args.precision, n_batches, run.n_slices - (n_batches - 1) * batch, name)
     if args.profile_out:
         from paper_2212_04749_amd import planner as P
         st = P.Structure.from_network(net, w.open_qubits)
@@ -495,10 +507,15 @@ def main():
         "dtype": "complex64" if args.precision == "c64" else "complex-half",
         "data": "synthetic",
         "complex_tflops": 8 * cmac_timed / (ms_step / 1e3) / 1e12,
-        # whole-step rate over the FP32 MFMA peak (complex64 runs all its
-        # GEMM steps on FP32 MFMA; complex-half mixes FP32 and FP16 steps)
-        "mfma_peak_frac": (8 * cmac_timed / (ms_step / 1e3) / 1e12 / PEAK_TFLOPS["fp32"]
-                           if args.precision == "c64" else None),
+        # whole-step rate over the MFMA peak of the precision (FP32 for
+        # complex64, FP16 for complex-half, whose stem still runs on FP32)
+        "mfma_peak_frac": 8 * cmac_timed / (ms_step / 1e3) / 1e12 /
+                          PEAK_TFLOPS["fp32" if args.precision == "c64" else "fp16"],
+        # sum over the steps of each one's roofline time (the larger of its
+        # flops over the MFMA peak of its kernel and its algorithmic bytes
+        # over 8 TB/s), over the measured step time
+        "step_roofline_ms": t_roof_ms,
+        "step_roofline_frac": t_roof_ms / ms_step,
         "xeb": xeb,
         "error_vs_fp64": err,
         "plan_s": t_plan,
