@@ -21,6 +21,20 @@ __device__ __forceinline__ gptr<T> gmem(uint64_t a) {
   return (gptr<T>)a;
 }
 
+// Offset tables are written when a plan is bound and only read by the
+// kernels.  A lookup at a wave-uniform index (a k step) through a constant
+// (address space 4) pointer compiles to scalar loads, which count on the
+// LDS/scalar wait counter: waiting for its result inside a k loop then does
+// not also wait for the operand loads in flight, which complete in order on
+// the vector-memory counter.
+template <typename T>
+using cptr = __attribute__((address_space(4))) T*;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> cmem(uint64_t a) {
+  return (cptr<T>)a;
+}
+
 // unsigned atomic max on a workspace word (float bits of non-negative values)
 __device__ __forceinline__ void gmax_u32(uint64_t a, uint32_t v) { atomicMax((uint32_t*)a, v); }
 

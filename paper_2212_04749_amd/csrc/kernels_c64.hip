@@ -60,6 +60,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
   __shared__ uint32_t s_mx[REC ? TN : 1];  // per-slot maxima (float bits)
 
   const gptr<const uint32_t> tab = gmem<const uint32_t>(ws + d.tab_off);
+  const cptr<const uint32_t> ctab = cmem<const uint32_t>(ws + d.tab_off);  // k-step lookups
   const gptr<const int32_t> glA = gmem<const int32_t>(ws + d.A.gmap_off);
   const gptr<const int32_t> glB = gmem<const int32_t>(ws + d.B.gmap_off);
   const int tid = threadIdx.x;
@@ -183,11 +184,11 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
 
     // k offsets run one step ahead of the loads that use them, so that their
     // table reads are in flight during a whole step of MFMA work
-    uint32_t kba = tlook(tab + TAB_AK * kTabSize, 0u), kbb = tlook(tab + TAB_BK * kTabSize, 0u);
+    uint32_t kba = tlook(ctab + TAB_AK * kTabSize, 0u), kbb = tlook(ctab + TAB_BK * kTabSize, 0u);
     gload(kba, kbb);
     if (ksteps > 1) {
-      kba = tlook(tab + TAB_AK * kTabSize, (uint32_t)TK);
-      kbb = tlook(tab + TAB_BK * kTabSize, (uint32_t)TK);
+      kba = tlook(ctab + TAB_AK * kTabSize, (uint32_t)TK);
+      kbb = tlook(ctab + TAB_BK * kTabSize, (uint32_t)TK);
     }
     lstore(0);
     __syncthreads();
@@ -196,8 +197,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
       if (ks + 1 < ksteps) {
         gload(kba, kbb);
         if (ks + 2 < ksteps) {
-          kba = tlook(tab + TAB_AK * kTabSize, (uint32_t)(ks + 2) * TK);
-          kbb = tlook(tab + TAB_BK * kTabSize, (uint32_t)(ks + 2) * TK);
+          kba = tlook(ctab + TAB_AK * kTabSize, (uint32_t)(ks + 2) * TK);
+          kbb = tlook(ctab + TAB_BK * kTabSize, (uint32_t)(ks + 2) * TK);
         }
       }
 #pragma unroll

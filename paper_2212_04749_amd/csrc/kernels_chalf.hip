@@ -43,13 +43,6 @@ __device__ __forceinline__ __half2 bits_h2(uint32_t u) {
   return h;
 }
 
-// element i of an operand as stored: a half2 in .x (FP16 storage) or the
-// two FP32 words
-__device__ __forceinline__ u32x2 ld_raw(uint64_t base, uint32_t i, int half) {
-  if (half) return u32x2{ldg_u32(base, i), 0u};
-  return gmem<const u32x2>(base)[i];
-}
-
 // as half2 bits: FP16 storage as is, FP32 storage scaled by c and rounded
 // to nearest
 __device__ __forceinline__ uint32_t to_h2bits(u32x2 raw, int half, float c) {
@@ -57,11 +50,33 @@ __device__ __forceinline__ uint32_t to_h2bits(u32x2 raw, int half, float c) {
   return h2bits(__float22half2_rn(make_float2(__uint_as_float(raw.x) * c, __uint_as_float(raw.y) * c)));
 }
 
+// an operand's staged elements: one half2 word (FP16 storage) or two FP32
+// words
+template <bool H>
+struct AStage;
+template <>
+struct AStage<true> {
+  typedef uint32_t type;
+  static __device__ __forceinline__ type load(uint64_t base, uint32_t i) { return ldg_u32(base, i); }
+  static __device__ __forceinline__ uint32_t bits(type r, float) { return r; }
+};
+template <>
+struct AStage<false> {
+  typedef u32x2 type;
+  static __device__ __forceinline__ type load(uint64_t base, uint32_t i) { return gmem<const u32x2>(base)[i]; }
+  static __device__ __forceinline__ uint32_t bits(type r, float c) { return to_h2bits(r, 0, c); }
+};
+
 // TM = 32*RM*WM values of m, TN = 16*RN*WN complex n, TK complex k (multiple of 4)
 // FAN: fan-out tiles as in k_mfma (desc.h): the TN columns are slots of
 // 2^nbits columns, one per output instance sharing the A instance; every
 // slot has its own B scale, output exponent and recorded maximum.
-template <int RM, int RN, int WM, int WN, int TK, bool FAN>
+// HA, HB: A, B stored in FP16 (the launcher picks the instance from the
+// step, so that the loads carry no storage branches).
+// Per-column data (C column offsets; for fan tiles each slot's output base,
+// factors and exponent) is kept in LDS, shared by the waves, rather than in
+// per-lane registers.
+template <int RM, int RN, int WM, int WN, int TK, bool FAN, bool HA, bool HB>
 __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
   constexpr int NT = 64 * WM * WN;
   constexpr int TM = 32 * RM * WM;
@@ -77,14 +92,18 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
   constexpr int APAIR = 2 * TM + 8;  // u32 per k pair (padded)
   __shared__ __attribute__((aligned(16))) uint32_t As[2][(TK / 2) * APAIR];
   __shared__ __attribute__((aligned(16))) uint32_t Bs[2][(TK / 2) * TN * 4];
-  // fan-out slots: output factor, output exponent, FP32-load factor of B,
-  // recorded maximum (float bits)
+  // C offset of each of the tile's TN columns; fan-out slots: output base
+  // (workspace offset, 0 = empty slot), output factor, output exponent,
+  // FP32-load factor of B, recorded maximum (float bits)
+  __shared__ uint32_t s_cn[TN];
+  __shared__ uint64_t s_cbase[FAN ? TN : 1];
   __shared__ float s_f[FAN ? TN : 1];
   __shared__ int s_e[FAN ? TN : 1];
-  __shared__ float s_cb[FAN ? TN : 1];
+  __shared__ float s_fb[FAN ? TN : 1];
   __shared__ uint32_t s_mx[FAN ? TN : 1];
 
   const gptr<const uint32_t> tab = gmem<const uint32_t>(ws + d.tab_off);
+  const cptr<const uint32_t> ctab = cmem<const uint32_t>(ws + d.tab_off);  // k-step lookups
   const gptr<const int32_t> glA = gmem<const int32_t>(ws + d.A.gmap_off);
   const gptr<const int32_t> glB = gmem<const int32_t>(ws + d.B.gmap_off);
   const int tid = threadIdx.x;
@@ -153,7 +172,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
       cb = ldexpf(1.f, -eb);
       mxb *= cb;
     }
-    const int ha = d.A.half, hb = d.B.half;
+    if (tid < TN) s_cn[tid] = tlook(tab + TAB_CN * kTabSize, FAN ? (tid & nmask) : n0 + tid);
     if (FAN) {
       // per-slot scales: B's exponent and load factor, the output exponent
       if (tid < slots) {
@@ -164,7 +183,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
           const HalfScale sg = ldg_scale(scB, operand_instance(d.B, glB, jg, s, sigma));
           int ebg = sg.e;
           float mxbg = __uint_as_float(sg.mx);
-          if (!hb && mxbg > 0.f) {
+          if (!HB && mxbg > 0.f) {
             int ex;
             frexpf(mxbg, &ex);
             ebg = ex - 14;
@@ -177,13 +196,14 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
           f = ldexpf(1.f, 15 - ex);
           e = ea + ebg + ex - 15;
         }
+        s_cbase[tid] = jg < 0 ? 0 : d.c_off + (uint64_t)(s * d.w + jg) * d.c_inst_bytes;
         s_f[tid] = f;
         s_e[tid] = e;
-        s_cb[tid] = cbg;
+        s_fb[tid] = cbg;
         s_mx[tid] = 0u;
       }
-      __syncthreads();
     }
+    __syncthreads();  // the column data above is read by every wave
 
     uint32_t aoff[EA], boff[EB];
     int akk[EA], bkk[EB], amm[EA], bnn[EB];
@@ -194,7 +214,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
       akk[e] = flat / TM;
       aoff[e] = tlook(tab + TAB_AM * kTabSize, m0 + amm[e]) + tab[TAB_AK * kTabSize + akk[e]];
     }
-    uint64_t pbe[EB];  // B instance of each element (fan tiles: its slot's; 0 = empty slot)
+    uint64_t pbe[EB];  // B instance of each element (fan tiles: its slot's)
     float cbe[EB];
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
@@ -204,8 +224,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
       if (FAN) {
         const int g = bnn[e] >> d.nbits;
         const int jg = fj[g];
-        pbe[e] = jg < 0 ? 0 : ws + d.B.off + operand_instance(d.B, glB, jg, s, sigma) * d.B.inst_bytes;
-        cbe[e] = s_cb[g];
+        // an empty slot reads slot 0's B into columns that are never stored
+        pbe[e] = ws + d.B.off + operand_instance(d.B, glB, jg < 0 ? j : jg, s, sigma) * d.B.inst_bytes;
+        cbe[e] = s_fb[g];
         boff[e] = tlook(tab + TAB_BN * kTabSize, bnn[e] & nmask) + tab[TAB_BK * kTabSize + bkk[e]];
       } else {
         pbe[e] = pb;
@@ -217,20 +238,21 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
     // FP32 -> FP16 conversion happens when the tile is written to LDS, after
     // the MFMA work of the current step, so the loads are not waited for
     // inside the load phase
-    u32x2 ra[EA], rb[EB];
+    typename AStage<HA>::type ra[EA];
+    typename AStage<HB>::type rb[EB];
     auto gload = [&](uint32_t kba, uint32_t kbb) {
 #pragma unroll
-      for (int e = 0; e < EA; ++e) ra[e] = ld_raw(pa, aoff[e] + kba, ha);
+      for (int e = 0; e < EA; ++e) ra[e] = AStage<HA>::load(pa, aoff[e] + kba);
 #pragma unroll
-      for (int e = 0; e < EB; ++e) rb[e] = (!FAN || pbe[e]) ? ld_raw(pbe[e], boff[e] + kbb, hb) : u32x2{0u, 0u};
+      for (int e = 0; e < EB; ++e) rb[e] = AStage<HB>::load(pbe[e], boff[e] + kbb);
     };
     auto lstore = [&](int buf) {
 #pragma unroll
       for (int e = 0; e < EA; ++e)
-        As[buf][(akk[e] >> 1) * APAIR + 2 * amm[e] + (akk[e] & 1)] = to_h2bits(ra[e], ha, ca);
+        As[buf][(akk[e] >> 1) * APAIR + 2 * amm[e] + (akk[e] & 1)] = AStage<HA>::bits(ra[e], ca);
 #pragma unroll
       for (int e = 0; e < EB; ++e) {
-        const uint32_t h = to_h2bits(rb[e], hb, cbe[e]);
+        const uint32_t h = AStage<HB>::bits(rb[e], cbe[e]);
         const uint32_t re = h & 0xffffu, im = h >> 16;
         const int base = (((bkk[e] >> 1) * TN + bnn[e]) * 2) * 2 + (bkk[e] & 1);
         Bs[buf][base] = re | ((im ^ 0x8000u) << 16);  // (Br, -Bi)
@@ -246,27 +268,17 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][q][r] = 0.f;
 
-    // output offsets of this lane, fetched before the k loop (see k_mfma)
-    uint32_t om[RM], ocn[RN][8];
-    int32_t jgv[RN][8];
+    // output offsets of this lane's m values, fetched before the k loop
+    uint32_t om[RM];
 #pragma unroll
     for (int i = 0; i < RM; ++i) om[i] = tlook(tab + TAB_CM * kTabSize, m0 + (wm * RM + i) * 32 + l32);
-#pragma unroll
-    for (int q = 0; q < RN; ++q)
-#pragma unroll
-      for (int rr = 0; rr < 8; ++rr) {
-        const int row = 8 * (rr >> 1) + 4 * half + 2 * (rr & 1);
-        const uint32_t n = n0 + (wn * RN + q) * 16 + (row >> 1);
-        ocn[q][rr] = tlook(tab + TAB_CN * kTabSize, FAN ? (n & nmask) : n);
-        jgv[q][rr] = FAN ? fj[n >> d.nbits] : 0;
-      }
 
     // k offsets one step ahead of the loads that use them
-    uint32_t kba = tlook(tab + TAB_AK * kTabSize, 0u), kbb = tlook(tab + TAB_BK * kTabSize, 0u);
+    uint32_t kba = tlook(ctab + TAB_AK * kTabSize, 0u), kbb = tlook(ctab + TAB_BK * kTabSize, 0u);
     gload(kba, kbb);
     if (ksteps > 1) {
-      kba = tlook(tab + TAB_AK * kTabSize, (uint32_t)TK);
-      kbb = tlook(tab + TAB_BK * kTabSize, (uint32_t)TK);
+      kba = tlook(ctab + TAB_AK * kTabSize, (uint32_t)TK);
+      kbb = tlook(ctab + TAB_BK * kTabSize, (uint32_t)TK);
     }
     lstore(0);
     __syncthreads();
@@ -275,8 +287,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
       if (ks + 1 < ksteps) {
         gload(kba, kbb);
         if (ks + 2 < ksteps) {
-          kba = tlook(tab + TAB_AK * kTabSize, (uint32_t)(ks + 2) * TK);
-          kbb = tlook(tab + TAB_BK * kTabSize, (uint32_t)(ks + 2) * TK);
+          kba = tlook(ctab + TAB_AK * kTabSize, (uint32_t)(ks + 2) * TK);
+          kbb = tlook(ctab + TAB_BK * kTabSize, (uint32_t)(ks + 2) * TK);
         }
       }
 #pragma unroll
@@ -315,23 +327,25 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
 #pragma unroll
       for (int rr = 0; rr < 8; ++rr) {
         const int r = 2 * rr;
+        const int row = 8 * (rr >> 1) + 4 * half + 2 * (rr & 1);
+        const int nl = (wn * RN + q) * 16 + (row >> 1);  // column within the tile
+        const uint32_t ocn = s_cn[nl];
         uint64_t dst = pc;
         bool live = true;
         float fo = f;
         int g = 0;
         if (FAN) {
-          const int row = 8 * (rr >> 1) + 4 * half + 2 * (rr & 1);
-          g = (int)(((uint32_t)(wn * RN + q) * 16 + (row >> 1)) >> d.nbits);
-          const int jg = jgv[q][rr];  // uniform over the 32 lanes of a half-wave (one n)
-          live = jg >= 0;
-          dst = ws + d.c_off + (s * d.w + (live ? jg : 0)) * d.c_inst_bytes;
+          g = nl >> d.nbits;
+          const uint64_t cb = s_cbase[g];  // uniform over the 32 lanes of a half-wave (one n)
+          live = cb != 0;
+          dst = ws + cb;
           fo = s_f[g];
         }
         float v = 0.f;
 #pragma unroll
         for (int i = 0; i < RM; ++i) {
           const __half2 h = __float22half2_rn(make_float2(acc[i][q][r] * fo, acc[i][q][r + 1] * fo));
-          if (live) stg_u32(dst, om[i] + ocn[q][rr], h2bits(h));
+          if (live) stg_u32(dst, om[i] + ocn, h2bits(h));
           const float2 back = __half22float2(h);
           v = fmaxf(v, fmaxf(fabsf(back.x), fabsf(back.y)));
         }
@@ -353,7 +367,6 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
           if (s_mx[tid] > 0u) max_scale_mx(ws + d.c_scale_off, s * d.w + jg, s_mx[tid]);
         }
       }
-      __syncthreads();  // the slot arrays are rewritten by the next tile
     } else {
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
@@ -362,6 +375,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
         if (mx > 0.f) max_scale_mx(ws + d.c_scale_off, inst, __float_as_uint(mx));
       }
     }
+    __syncthreads();  // the column and slot arrays are rewritten by the next tile
   }
 }
 
@@ -462,6 +476,22 @@ bool mfma_h_fan_config_fits(int cfg, int mbits, int nbits, int kbits, int fan_tn
   return (1 << c.tn_bits) == fan_tn && nbits < c.tn_bits && mbits >= c.tm_bits && kbits >= c.tk_bits;
 }
 
+template <bool FAN, bool HA, bool HB>
+static hipError_t launch_mfma_h_cfg(const NodeDesc& d, int cfg, unsigned grid, uint64_t ws, const int64_t* sig,
+                                    hipStream_t st) {
+  switch (cfg) {
+    case 0: hipLaunchKernelGGL((k_mfma_h<2, 2, 2, 2, 16, FAN, HA, HB>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 1: hipLaunchKernelGGL((k_mfma_h<2, 1, 2, 2, 16, FAN, HA, HB>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 2: hipLaunchKernelGGL((k_mfma_h<1, 1, 2, 2, 16, FAN, HA, HB>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 3: hipLaunchKernelGGL((k_mfma_h<4, 1, 2, 2, 16, FAN, HA, HB>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 4: hipLaunchKernelGGL((k_mfma_h<2, 1, 2, 2, 8, FAN, HA, HB>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 5: hipLaunchKernelGGL((k_mfma_h<4, 2, 2, 2, 16, FAN, HA, HB>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 6: hipLaunchKernelGGL((k_mfma_h<2, 2, 2, 2, 8, FAN, HA, HB>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <bool FAN>
 static hipError_t launch_mfma_h_t(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
   if (d.n_inst == 0) return hipSuccess;
@@ -472,17 +502,12 @@ static hipError_t launch_mfma_h_t(const NodeDesc& d, int cfg, uint64_t ws, const
   const int64_t units = FAN ? (d.n_inst / d.w) * d.n_fan : d.n_inst;
   const int64_t tiles = ((int64_t)1 << (d.mbits - c.tm_bits)) * (FAN ? 1 : ((int64_t)1 << (d.nbits - c.tn_bits)));
   const unsigned grid = grid_for(units * tiles);
-  switch (cfg) {
-    case 0: hipLaunchKernelGGL((k_mfma_h<2, 2, 2, 2, 16, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 1: hipLaunchKernelGGL((k_mfma_h<2, 1, 2, 2, 16, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 2: hipLaunchKernelGGL((k_mfma_h<1, 1, 2, 2, 16, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 3: hipLaunchKernelGGL((k_mfma_h<4, 1, 2, 2, 16, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 4: hipLaunchKernelGGL((k_mfma_h<2, 1, 2, 2, 8, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 5: hipLaunchKernelGGL((k_mfma_h<4, 2, 2, 2, 16, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 6: hipLaunchKernelGGL((k_mfma_h<2, 2, 2, 2, 8, FAN>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    default: return hipErrorInvalidValue;
+  if (d.A.half) {
+    if (d.B.half) return launch_mfma_h_cfg<FAN, true, true>(d, cfg, grid, ws, sig, st);
+    return launch_mfma_h_cfg<FAN, true, false>(d, cfg, grid, ws, sig, st);
   }
-  return hipGetLastError();
+  if (d.B.half) return launch_mfma_h_cfg<FAN, false, true>(d, cfg, grid, ws, sig, st);
+  return launch_mfma_h_cfg<FAN, false, false>(d, cfg, grid, ws, sig, st);
 }
 
 hipError_t launch_mfma_h(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {

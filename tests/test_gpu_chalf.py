@@ -126,3 +126,51 @@ def test_chalf_permutation_scaling_c2_size():
     run.close()
     ref = closed_forms.permutation_amplitudes(circ, words)
     assert rel_err(got, ref) <= 3e-3
+
+
+
+FP16_TILE_CONFIGS = 7
+
+
+def force_fp16_configs(run, cache, check):
+    """Force each FP16 MFMA tile configuration c, through the tuning cache, on
+    every FP16-stored MFMA step class of run's plan, and call check(c) after
+    each; returns the kernel ids the profile showed (300 + c plain tiles,
+    400 + c fan-out tiles)."""
+    run.autotune(reps=1, cache_path=cache)
+    tuned = json.load(open(cache))
+    hkeys = [k for k in tuned if k.startswith("chalf/h/")]
+    say(f"FP16 MFMA step classes: {hkeys}")
+    assert hkeys
+    ran = set()
+    for c in range(FP16_TILE_CONFIGS):
+        forced = dict(tuned)
+        forced.update({k: c for k in hkeys})
+        with open(cache, "w") as f:
+            json.dump(forced, f)
+        run.autotune(reps=1, cache_path=cache)
+        kids = {kid for _, kid, _, _ in run.profile() if kid >= 300}
+        ran |= kids
+        check(c, sorted(kids))
+    say(f"FP16 kernels exercised: {sorted(ran)}")
+    return ran
+
+
+def test_every_fp16_fan_out_configuration(tmp_path):
+    # a plan whose widest step (w ~ 4000, m/n/k = 9/0/10 bits) is stored in
+    # FP16 and runs as fan-out tiles: every FP16 tile configuration (32- and
+    # 64-column fan tables) against the state vector
+    require_gpu()
+    circ = random_circuit(GridSpec(5, 5), 12, 8)
+    words = uniform_bitstrings(25, 4096, 9)
+    ref = statevector.amplitudes(circ, words)
+    run = contraction(circ, words, trials=4)
+
+    def check(c, kids):
+        err = rel_err(run.amplitudes(), ref)
+        say(f"FP16 tile configuration {c}: kernels {kids}, rel err {err:.2e}")
+        assert err <= 3e-3, f"configuration {c}"
+
+    ran = force_fp16_configs(run, str(tmp_path / "tune.json"), check)
+    assert {kid - 400 for kid in ran if kid >= 400} == set(range(FP16_TILE_CONFIGS))
+    run.close()

@@ -10,6 +10,8 @@ scaling of the 6x6 depth-14 workload (36 qubits, 8 open legs, 64 groups,
 2^8 slices) against exact values; a neighbouring slice must give zero.
 """
 
+import functools
+
 import numpy as np
 import pytest
 
@@ -48,18 +50,25 @@ def expected_block(circ, groups, opens):
     return a.reshape(len(groups), 1 << len(opens))
 
 
-@pytest.mark.parametrize("precision,tol", [("c64", 1e-5), ("chalf", 3e-3)])
-def test_c3_size_permutation_circuit(precision, tol):
-    require_gpu()
-    from paper_2212_04749_amd import api, planner
+@functools.lru_cache(maxsize=1)
+def c3_permutation_plan():
+    from paper_2212_04749_amd import planner
     from paper_2212_04749_amd.circuit_tn import build_network
     w = CONFIGS["C3"]
     circ = permutation_circuit(w.grid, w.depth, 303)
+    net = build_network(circ)
+    say("C3-size permutation: planning")
+    pl = planner.find_plan(net, w.bitstrings(), w.open_qubits, w.cap, trials=4, exact_slices=8, refine_top=1)
+    return w, circ, net, pl
+
+
+@pytest.mark.parametrize("precision,tol", [("c64", 1e-5), ("chalf", 3e-3)])
+def test_c3_size_permutation_circuit(precision, tol):
+    require_gpu()
+    from paper_2212_04749_amd import api
+    w, circ, net, pl = c3_permutation_plan()
     groups = w.bitstrings()
     opens = w.open_qubits
-    net = build_network(circ)
-    say(f"C3-size permutation {precision}: planning")
-    pl = planner.find_plan(net, groups, opens, w.cap, trials=4, exact_slices=8, refine_top=1)
     spec = api.PlanSpec(pl.pairs, pl.sliced, tuple(opens), w.cap)
     run = api.Contraction(net, spec, groups, precision=precision, slice_batch=1)
     sigma = trajectory_slice(net, pl.sliced, closed_forms.permutation_trajectory(circ))
@@ -77,4 +86,32 @@ def test_c3_size_permutation_circuit(precision, tol):
     run.synchronize()
     a2 = amps2.cpu().numpy()
     assert np.max(np.abs(a2)) <= 1e-6 * 2.0 ** -18
+    run.close()
+
+
+def test_c3_size_permutation_every_fp16_configuration(tmp_path):
+    # the complex-half plan of the 6x6 workload has plain FP16 MFMA steps
+    # (no fan-out): every FP16 tile configuration forced on them, against the
+    # exact amplitudes of the one contributing slice
+    require_gpu()
+    from paper_2212_04749_amd import api
+    from test_gpu_chalf import force_fp16_configs
+    w, circ, net, pl = c3_permutation_plan()
+    groups = w.bitstrings()
+    opens = w.open_qubits
+    spec = api.PlanSpec(pl.pairs, pl.sliced, tuple(opens), w.cap)
+    run = api.Contraction(net, spec, groups, precision="chalf", slice_batch=1)
+    sigma = trajectory_slice(net, pl.sliced, closed_forms.permutation_trajectory(circ))
+    ref = expected_block(circ, groups, opens)
+
+    def check(c, kids):
+        amps = run.execute(None, sigma, sigma + 1)
+        run.synchronize()
+        a = amps.cpu().numpy()
+        err = rel_err(a[..., 0] + 1j * a[..., 1], ref)
+        say(f"FP16 tile configuration {c}: kernels {kids}, rel err {err:.2e}")
+        assert err <= 3e-3, f"configuration {c}"
+
+    ran = force_fp16_configs(run, str(tmp_path / "tune.json"), check)
+    assert any(300 <= kid < 400 for kid in ran)
     run.close()
