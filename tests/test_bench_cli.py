@@ -34,3 +34,18 @@ def test_traffic_record_needs_unchanged_sources(tmp_path, monkeypatch):
     (prof / "x.md").write_text("<!-- traffic " + json.dumps(rec) + " -->\n")
     assert bench.pmc_traffic("CX", "c64", 7) == 123.0
     assert bench.pmc_traffic("CX", "c64", 8) is None
+
+
+def test_shipped_tuning_file_is_valid():
+    # the tile configurations bench.py loads by default: one entry per step
+    # class, each an index into the configuration table of its kernel
+    import json
+    import re
+    from paper_2212_04749_amd import binding as B
+    tuned = json.load(open(os.path.join(ROOT, "paper_2212_04749_amd", "tuning_mi355x.json")))
+    assert tuned
+    for key, cfg in tuned.items():
+        m = re.fullmatch(r"(c64|chalf)/(f|h)/(fan/)?(\d+),(\d+),(\d+)/(\d+)", key)
+        assert m, key
+        bound = B.matnc_mfma_config_count() if m.group(2) == "f" else 7
+        assert 0 <= cfg < bound, key
