@@ -395,7 +395,7 @@ def run_uneven(args) -> None:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU slice sharding is not built",
+        print(json.dumps({"error": "bench.py runs on one GPU only; multi-GPU slice sharding is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.copy_probe:
