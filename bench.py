@@ -57,6 +57,9 @@ def parse():
     p.add_argument("--replan", action="store_true",
                    help="53-qubit workload: search a plan instead of loading the stored one")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--beside", action="store_true",
+                   help="complex64 runs: also time complex-half on the same plan (default for the small workloads)")
+    p.add_argument("--no-beside", action="store_true")
     p.add_argument("--no-autotune", action="store_true", help="keep the heuristic MFMA tile choice")
     p.add_argument("--profile-out", default="", help="write the per-step profile as JSON")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -392,6 +395,48 @@ def run_uneven(args) -> None:
     print(json.dumps(out), flush=True)
 
 
+def beside_pass(api, torch, net, spec, words, name, batch, args):
+    """The same workload and plan in complex-half, timed with the same
+    protocol (every step a full pass from an empty stem cache), for the
+    complex-half rate beside the complex64 one."""
+    run = api.Contraction(net, spec, words, precision="chalf", slice_batch=batch)
+    if not args.no_autotune:
+        run.autotune(reps=3, cache_path=tuning_cache())
+    amps = run.new_amplitudes()
+
+    def step():
+        run.reset_cache()
+        with torch.cuda.stream(run.stream):
+            amps.zero_()
+        run.execute(amps)
+        return run.xeb_dev(amps)
+
+    for _ in range(args.warmup):
+        step()
+        run.synchronize()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(run.stream)
+    for _ in range(args.steps):
+        x = step()
+    ev1.record(run.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    log(f"complex-half beside: {ms:.2f} ms/step")
+    a = amps.cpu().numpy()
+    err = reference_error(name, run, a[..., 0] + 1j * a[..., 1])
+    n_batches = -(-run.n_slices // batch)
+    roof, _, t_roof_ms = roofline(run, "chalf", n_batches, run.n_slices - (n_batches - 1) * batch, name)
+    info = run.info
+    tflops = 8 * info.cmac_total / (ms / 1e3) / 1e12
+    out = {"dtype": "complex-half", "ms_per_step": ms, "value": info.n_amplitudes / (ms / 1e3),
+           "unit": "amplitudes/s", "complex_tflops": tflops, "mfma_peak_frac": tflops / PEAK_TFLOPS["fp16"],
+           "step_roofline_frac": t_roof_ms / ms, "xeb": float(x.cpu().item()), "error_vs_fp64": err,
+           "roofline": roof}
+    run.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -582,8 +627,11 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
     run.close()
+    if args.precision == "c64" and full and not args.no_beside and (args.beside or name in ("C1", "C2")):
+        torch.cuda.empty_cache()
+        out["complex_half"] = beside_pass(api, torch, net, spec, words, name, batch, args)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
