@@ -55,7 +55,7 @@ def parse():
                    help="time N consecutive slices (seeded start) instead of all of them and project the "
                         "full-job rate (the large workloads); 0 = every slice")
     p.add_argument("--replan", action="store_true",
-                   help="53-qubit workload: search a plan instead of loading the stored one")
+                   help="6x6 and 53-qubit workloads: search a plan instead of loading the stored one")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--beside", action="store_true",
                    help="complex64 runs: also time complex-half on the same plan (default for the small workloads)")
@@ -468,10 +468,11 @@ def main():
     # at least the workload's slice count; a cheaper plan that needs more
     # sliced indices to meet the rank cap keeps its real count
     pt = args.partition_trials if args.partition_trials >= 0 else (16 if name in ("C3", "C4") else 0)
-    if name == "C4" and not args.replan:
-        # the stored plan (plans/make_c4.py: tens of minutes of planning)
-        from paper_2212_04749_amd.plans import make_c4
-        e = make_c4.load()
+    if name in ("C3", "C4") and not args.replan:
+        # the stored plan (plans/make_c3.py, make_c4.py: minutes to tens of
+        # minutes of host planning)
+        import importlib
+        e = importlib.import_module(f"paper_2212_04749_amd.plans.make_{name.lower()}").load()
         pairs = [tuple(x) for x in e["pairs"]]
         st0 = planner.Structure.from_network(net, w.open_qubits)
         plan = planner.Plan(pairs, list(e["sliced"]), planner.costs(

@@ -193,16 +193,18 @@ def test_memory_cap_bounds_multi_amplitude_tensors():
 def _check_stored_plan(w, e):
     net = build_network(w.circuit())
     words = w.bitstrings()
-    st = P.Structure.from_network(net, ())
+    opens = list(e.get("open_qubits", ()))
+    st = P.Structure.from_network(net, opens)
     pairs = [tuple(x) for x in e["pairs"]]
     smask = sum(1 << i for i in e["sliced"])
     tree = P.build_tree(st, pairs, smask)
     wd = P.widths(P.build_tree(st, pairs), words)
     assert max(m.bit_count() for m in tree.masks) <= e["cap"]
-    assert max(math.log2(wd[v]) + tree.masks[v].bit_count() for v in range(len(tree.masks))) <= e["mem_cap"] + 1e-9
+    if "mem_cap" in e:
+        assert max(math.log2(wd[v]) + tree.masks[v].bit_count() for v in range(len(tree.masks))) <= e["mem_cap"] + 1e-9
     ranks, ids, data = api.network_arrays(net)
     h = B.matnc_network_create(ranks, ids, data, net.n_qubits, net.output_index)
-    p = B.matnc_plan_create(h, pairs, e["sliced"], [], words, 0, e["cap"], 1)
+    p = B.matnc_plan_create(h, pairs, e["sliced"], opens, words, 0, e["cap"], 1)
     info = B.matnc_plan_info(p)
     assert info.n_slices == 2 ** len(e["sliced"]) and info.max_rank <= e["cap"]
     assert math.isclose(info.cmac_total, e["cmac_total"], rel_tol=1e-9)
@@ -211,11 +213,12 @@ def _check_stored_plan(w, e):
 
 
 def test_stored_plans_are_valid_library_inputs():
-    # the stored trees of the 53-qubit workload and of the uneven batch meet
-    # their rank and memory caps, and the library's cost figures agree with
-    # the planner's
-    from paper_2212_04749_amd.plans import make_c4, make_c5
+    # the stored trees of the 6x6 and 53-qubit workloads and of the uneven
+    # batch meet their rank and memory caps, and the library's cost figures
+    # agree with the planner's
+    from paper_2212_04749_amd.plans import make_c3, make_c4, make_c5
     from workload.configs import uneven_batch_c5
+    _check_stored_plan(CONFIGS["C3"], make_c3.load())
     _check_stored_plan(CONFIGS["C4"], make_c4.load())
     plans = make_c5.load()
     for w in uneven_batch_c5():
