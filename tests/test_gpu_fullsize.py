@@ -115,3 +115,36 @@ def test_c3_size_permutation_every_fp16_configuration(tmp_path):
     ran = force_fp16_configs(run, str(tmp_path / "tune.json"), check)
     assert any(300 <= kid < 400 for kid in ran)
     run.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("c64", 1e-5), ("chalf", 3e-3)])
+def test_c4_size_permutation_circuit(precision, tol):
+    # the 53-qubit workload's network structure and stored plan (8192
+    # slices), on a permutation circuit: the one contributing slice gives
+    # the exact amplitudes (modulus 2^-26.5, which also exercises the
+    # complex-half exponents) and a neighbouring slice gives zero
+    require_gpu()
+    from paper_2212_04749_amd import api
+    from paper_2212_04749_amd.circuit_tn import build_network
+    from paper_2212_04749_amd.plans import make_c4
+    w = CONFIGS["C4"]
+    circ = permutation_circuit(w.grid, w.depth, 404)
+    net = build_network(circ)
+    e = make_c4.load()
+    spec = api.PlanSpec([tuple(p) for p in e["pairs"]], e["sliced"], (), e["cap"])
+    words = w.bitstrings()
+    run = api.Contraction(net, spec, words, precision=precision, slice_batch=1)
+    sigma = trajectory_slice(net, e["sliced"], closed_forms.permutation_trajectory(circ))
+    say(f"53-qubit permutation {precision}: {run.n_slices} slices, slice {sigma}")
+    amps = run.execute(None, sigma, sigma + 1)
+    run.synchronize()
+    a = amps.cpu().numpy()
+    got = a[..., 0, 0] + 1j * a[..., 0, 1]
+    ref = closed_forms.permutation_amplitudes(circ, words)
+    assert np.allclose(np.abs(ref), 2.0 ** -26.5, rtol=1e-12)
+    assert rel_err(got, ref) <= tol
+    other = sigma ^ 1
+    amps2 = run.execute(None, other, other + 1)
+    run.synchronize()
+    assert np.max(np.abs(amps2.cpu().numpy())) <= 1e-6 * 2.0 ** -26.5
+    run.close()
