@@ -156,58 +156,68 @@ def reference_error(name, run, amps_np):
 
 
 def roofline(run, precision, n_batches, nb_last, workload):
-    """Aggregate a profiled pass per kernel; the dominant kernel's algorithmic
-    flops (MFMA) or bytes (streaming) per launch over its mean launch time."""
+    """Roofline of the dominant launch of a profiled pass.  Every contraction
+    step is one launch of one kernel configuration on one shape; the
+    dominant one is the step with the largest share of the pass
+    (slice-dependent steps run once per slice batch).  Its bound is the
+    larger of its algorithmic flops over the MFMA peak of its kernel and its
+    algorithmic bytes over the HBM peak, and achieved is that quantity per
+    launch over the launch's time.  Also returns per-kernel-id aggregates
+    and the pass's summed per-step roofline time (ms)."""
     prof = run.profile(0, min(run.slice_batch, run.n_slices))
     per = {}
+    steps = []
     t_roof = 0.0  # sum over steps of max(flops / MFMA peak, bytes / HBM peak), ms
-    for (ms, kid, cmac, by), dep in zip(prof, run.step_dep()):
+    for j, ((ms, kid, cmac, by), dep) in enumerate(zip(prof, run.step_dep())):
         if ms < 0:
             continue
         reps = n_batches if dep else 1
+        # 100/200 + c: FP32 MFMA (complex64, and the FP32 steps of
+        # complex-half); 300/400 + c: FP16 MFMA; 0: streaming (vector ALU)
         peak = PEAK_TFLOPS["fp16" if kid >= 300 else "fp32"]
-        t_roof += reps * max(8 * cmac / (peak * 1e12), by / (PEAK_HBM_GBS * 1e9)) * 1e3
+        tf, tb = 8 * cmac / (peak * 1e12), by / (PEAK_HBM_GBS * 1e9)
+        t_roof += reps * max(tf, tb) * 1e3
         e = per.setdefault(kid, {"ms": 0.0, "cmac": 0.0, "bytes": 0.0, "launches": 0})
         e["ms"] += ms * reps
         e["cmac"] += cmac * reps
         e["bytes"] += by * reps
         e["launches"] += reps
-    kid = max(per, key=lambda k: per[k]["ms"])
-    e = per[kid]
-    t = e["ms"] / 1e3
-    if kid >= 100:
-        # 100/200 + c: FP32 MFMA (complex64, and the FP32 steps of
-        # complex-half); 300/400 + c: FP16 MFMA
-        achieved = 8 * e["cmac"] / t / 1e12
-        r = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["fp16" if kid >= 300 else "fp32"],
-             "unit": "TFLOP/s"}
+        steps.append((ms * reps, j, ms, kid, cmac, by, reps, tf, tb, peak))
+    total = sum(x[0] for x in steps)
+    share, j, ms, kid, cmac, by, reps, tf, tb, peak = max(steps)
+    t = ms / 1e3
+    if kid >= 100 and tf >= tb:
+        r = {"bound": "mfma", "achieved": 8 * cmac / t / 1e12, "peak": peak, "unit": "TFLOP/s"}
     else:
-        achieved = e["bytes"] / t / 1e9
-        r = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+        r = {"bound": "hbm", "achieved": by / t / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     r["frac"] = r["achieved"] / r["peak"]
-    r["traffic"] = pmc_traffic(workload, precision, kid)
-    r["algorithmic_bytes_per_launch"] = e["bytes"] / e["launches"]
+    r["traffic"] = pmc_traffic(workload, precision, kid, j)
+    r["algorithmic_bytes_per_launch"] = by
+    r["algorithmic_flops_per_launch"] = 8 * cmac
     r["kernel"] = ("streaming" if kid < 100 else
                    f"{'fp16' if kid >= 300 else 'fp32'} mfma{' fan-out' if (kid // 100) % 2 == 0 else ''} "
-                   f"cfg {kid % 100}")
-    r["launches"] = e["launches"]
-    r["mean_launch_ms"] = e["ms"] / e["launches"]
-    r["share_of_step"] = e["ms"] / sum(v["ms"] for v in per.values())
+                   f"cfg {kid % 100}") + f", step {j}"
+    r["kernel_id"] = kid
+    r["step"] = j
+    r["launches"] = reps
+    r["mean_launch_ms"] = ms
+    r["share_of_step"] = share / total
     return r, per, t_roof
 
 
-def pmc_traffic(workload: str, precision: str, kernel_id: int):
-    """HBM bytes per launch of a kernel as measured by rocprofv3 counters
-    (FETCH_SIZE and WRITE_SIZE scaled by a copy-kernel calibration) and
-    recorded in profiles/*.md, or None when no record matches or the kernel
-    sources changed since the counters were taken."""
+def pmc_traffic(workload: str, precision: str, kernel_id: int, step: int):
+    """HBM bytes per launch of one step's kernel as measured by rocprofv3
+    counters (FETCH_SIZE and WRITE_SIZE scaled by a copy-kernel calibration)
+    and recorded in profiles/*.md, or None when no record matches or the
+    kernel sources changed since the counters were taken."""
     import glob
     import hashlib
     import re
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for m in re.finditer(r"<!-- traffic (\{.*?\}) -->", open(path).read()):
             rec = json.loads(m.group(1))
-            if (rec["workload"], rec["precision"], rec["kernel_id"]) != (workload, precision, kernel_id):
+            if (rec["workload"], rec["precision"], rec["kernel_id"], rec["step"]) != \
+                    (workload, precision, kernel_id, step):
                 continue
             same = all(os.path.exists(os.path.join(ROOT, f)) and
                        hashlib.sha256(open(os.path.join(ROOT, f), "rb").read()).hexdigest() == h

@@ -49,8 +49,11 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
   static_assert(EA * NT == TK * TM && EB * NT == TK * TN, "tile must split evenly over threads");
   constexpr int APL = TK * TM + 32;        // plane stride (floats), padded
   constexpr int BPL = TK * TN + 16;
+  // third B plane (-Bi) at 16 words mod 32 like the second, so that the two
+  // planes a half-wave reads (0 and BPL, or BP2 and 0) sit in different banks
+  constexpr int BP2 = 2 * BPL + 16;
   __shared__ float As[2][2 * APL];
-  __shared__ float Bs[2][2 * BPL];
+  __shared__ float Bs[2][BP2 + BPL];  // planes Br, Bi, -Bi
   // per-tile column data, shared by the waves instead of held per lane:
   // the C offset of each of the tile's TN columns, and for fan tiles the
   // B instance (byte offset) and output instance base of each slot
@@ -157,6 +160,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
       for (int e = 0; e < EB; ++e) {
         Bs[buf][bkk[e] * TN + bnn[e]] = rb[e].x;
         Bs[buf][BPL + bkk[e] * TN + bnn[e]] = rb[e].y;
+        Bs[buf][BP2 + bkk[e] * TN + bnn[e]] = -rb[e].y;
       }
     };
 
@@ -173,8 +177,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
     const int dsel = l32 & 1;       // 0: real column, 1: imaginary column
     const int ncol = l32 >> 1;
     // which B plane feeds this lane, and with which sign
-    const int bplane = (half ^ dsel) ? BPL : 0;  // (0,0)->Br (0,1)->Bi (1,0)->Bi (1,1)->Br
-    const float bsign = (half == 1 && dsel == 0) ? -1.f : 1.f;
+    // (half, dsel): (0,0) -> Br, (0,1) -> Bi, (1,0) -> -Bi, (1,1) -> Br, each
+    // read from its own plane so that no sign flip sits between the LDS
+    // read and the MFMA
+    const int bplane = (half ^ dsel) ? (half ? BP2 : BPL) : 0;
     const int aplane = half ? APL : 0;
 
     // output offsets of this lane's m values, fetched before the k loop
@@ -207,7 +213,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
 #pragma unroll
         for (int i = 0; i < RM; ++i) yv[i] = As[buf][aplane + kk * TM + (wm * RM + i) * 32 + l32];
 #pragma unroll
-        for (int q = 0; q < RN; ++q) xv[q] = bsign * Bs[buf][bplane + kk * TN + (wn * RN + q) * 16 + ncol];
+        for (int q = 0; q < RN; ++q) xv[q] = Bs[buf][bplane + kk * TN + (wn * RN + q) * 16 + ncol];
 #pragma unroll
         for (int i = 0; i < RM; ++i)
 #pragma unroll

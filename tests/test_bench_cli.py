@@ -21,19 +21,20 @@ def test_more_than_one_gpu_is_refused():
 def test_traffic_record_needs_unchanged_sources(tmp_path, monkeypatch):
     sys.path.insert(0, ROOT)
     import bench
-    rec = {"workload": "CX", "precision": "c64", "kernel_id": 7, "bytes_per_launch": 123,
+    rec = {"workload": "CX", "precision": "c64", "kernel_id": 7, "step": 3, "bytes_per_launch": 123,
            "sources": {"bench.py": "0" * 64}}
     prof = tmp_path / "profiles"
     prof.mkdir()
     (prof / "x.md").write_text("text\n<!-- traffic " + json.dumps(rec) + " -->\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     (tmp_path / "bench.py").write_text("changed")
-    assert bench.pmc_traffic("CX", "c64", 7) is None
+    assert bench.pmc_traffic("CX", "c64", 7, 3) is None
     import hashlib
     rec["sources"] = {"bench.py": hashlib.sha256(b"changed").hexdigest()}
     (prof / "x.md").write_text("<!-- traffic " + json.dumps(rec) + " -->\n")
-    assert bench.pmc_traffic("CX", "c64", 7) == 123.0
-    assert bench.pmc_traffic("CX", "c64", 8) is None
+    assert bench.pmc_traffic("CX", "c64", 7, 3) == 123.0
+    assert bench.pmc_traffic("CX", "c64", 8, 3) is None
+    assert bench.pmc_traffic("CX", "c64", 7, 4) is None
 
 
 def test_shipped_tuning_file_is_valid():
