@@ -223,3 +223,25 @@ def test_stored_plans_are_valid_library_inputs():
     plans = make_c5.load()
     for w in uneven_batch_c5():
         _check_stored_plan(w, plans[w.name])
+
+
+def test_c_program_uses_the_abi(tmp_path):
+    # the boundary from plain C: include/matnc.h + libmatnc.so, host calls
+    # only (network, plan, figures, an invalid tree, execute before bind)
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    B.lib()  # built
+    libdir = os.path.join(ROOT, "paper_2212_04749_amd")
+    exe = str(tmp_path / "plan_info")
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "c_abi", "plan_info.c"), "-L", libdir, "-lmatnc",
+                    f"-Wl,-rpath,{libdir}", "-o", exe], check=True, capture_output=True, text=True)
+    out = subprocess.run([exe], check=True, capture_output=True, text=True, timeout=120).stdout
+    assert "n_amplitudes 4 n_unique 4 n_slices 1 n_nodes 1 max_rank 1" in out
+    # S = 2^|{bond}| = 2 complex MACs per amplitude; S_k = 4 keys x 2
+    assert "cmac_single 2.0 cmac_multi 8.0" in out
+    assert f"bad tree rc {B.MATNC_E_INVALID} (invalid) message present" in out
+    assert f"execute before bind rc {B.MATNC_E_STATE}" in out
