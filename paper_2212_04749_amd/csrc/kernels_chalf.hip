@@ -37,16 +37,9 @@ __device__ __forceinline__ uint32_t h2bits(__half2 h) {
   return u;
 }
 
-__device__ __forceinline__ __half2 bits_h2(uint32_t u) {
-  __half2 h;
-  __builtin_memcpy(&h, &u, 4);
-  return h;
-}
 
-// as half2 bits: FP16 storage as is, FP32 storage scaled by c and rounded
-// to nearest
-__device__ __forceinline__ uint32_t to_h2bits(u32x2 raw, int half, float c) {
-  if (half) return raw.x;
+// an FP32 (re, im) pair as half2 bits, scaled by c and rounded to nearest
+__device__ __forceinline__ uint32_t f32pair_to_h2bits(u32x2 raw, float c) {
   return h2bits(__float22half2_rn(make_float2(__uint_as_float(raw.x) * c, __uint_as_float(raw.y) * c)));
 }
 
@@ -64,7 +57,7 @@ template <>
 struct AStage<false> {
   typedef u32x2 type;
   static __device__ __forceinline__ type load(uint64_t base, uint32_t i) { return gmem<const u32x2>(base)[i]; }
-  static __device__ __forceinline__ uint32_t bits(type r, float c) { return to_h2bits(r, 0, c); }
+  static __device__ __forceinline__ uint32_t bits(type r, float c) { return f32pair_to_h2bits(r, c); }
 };
 
 // TM = 32*RM*WM values of m, TN = 16*RN*WN complex n, TK complex k (multiple of 4)
