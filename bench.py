@@ -91,21 +91,26 @@ def copy_probe(mib: int) -> None:
 TUNING = os.path.join(ROOT, "paper_2212_04749_amd", "tuning_mi355x.json")
 
 
-def tuning_cache() -> str:
-    """Tile configurations for the autotuner: $MATNC_AUTOTUNE_CACHE if set,
-    else a scratch copy of the shipped MI355X choices (the step classes of
-    the default workloads, measured with this library), so that a default
-    run uses the configurations its profile was taken with; classes not in
-    the file are timed and added to the copy only."""
+def autotune(run) -> None:
+    """Pick tile configurations with the library's autotuner, starting from
+    $MATNC_AUTOTUNE_CACHE if set, else from a scratch copy of the shipped
+    MI355X choices (the step classes of the default workloads, measured with
+    this library), so that a default run uses the configurations its profile
+    was taken with; classes not in the file are timed and added to the copy
+    only, which is removed afterwards."""
     env = os.environ.get("MATNC_AUTOTUNE_CACHE")
     if env:
-        return env
+        run.autotune(reps=3, cache_path=env)
+        return
     import shutil
     import tempfile
     fd, path = tempfile.mkstemp(prefix="matnc_tune_", suffix=".json")
     os.close(fd)
-    shutil.copyfile(TUNING, path)
-    return path
+    try:
+        shutil.copyfile(TUNING, path)
+        run.autotune(reps=3, cache_path=path)
+    finally:
+        os.remove(path)
 
 
 def workload_description(name, w, info, spec):
@@ -411,7 +416,7 @@ def beside_pass(api, torch, net, spec, words, name, batch, args):
     complex-half rate beside the complex64 one."""
     run = api.Contraction(net, spec, words, precision="chalf", slice_batch=batch)
     if not args.no_autotune:
-        run.autotune(reps=3, cache_path=tuning_cache())
+        autotune(run)
     amps = run.new_amplitudes()
 
     def step():
@@ -503,7 +508,7 @@ def main():
     t_tune = 0.0
     if not args.no_autotune:
         t0 = time.perf_counter()
-        run.autotune(reps=3, cache_path=tuning_cache())
+        autotune(run)
         t_tune = time.perf_counter() - t0
     info = run.info
     log(f"plan {t_plan:.2f}s bind {t_bind:.2f}s autotune {t_tune:.2f}s workspace {info.workspace_bytes / 2**30:.2f} GiB "
