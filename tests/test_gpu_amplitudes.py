@@ -7,7 +7,7 @@ batch, |XEB - XEB_ref| <= 1e-4 (the stated bars for complex64).
 import numpy as np
 import pytest
 
-from gpu_util import rel_err, require_gpu, say
+from gpu_util import assert_close, rel_err, require_gpu, say
 from oracle import closed_forms, statevector, tn as otn, xeb as oxeb
 from workload import CONFIGS, GridSpec, permutation_circuit, product_circuit, random_circuit, uniform_bitstrings
 
@@ -28,7 +28,7 @@ def test_c1_against_statevector():
     run = contraction(circ, words)
     got = run.amplitudes()
     ref = statevector.amplitudes(circ, words)
-    assert rel_err(got, ref) <= 1e-5
+    assert_close(got, ref, 1e-5)
     f = run.xeb()
     assert abs(f - oxeb.linear_xeb(ref, 16)) <= 1e-4
     run.close()
@@ -44,7 +44,7 @@ def test_sliced_matches_unsliced_and_oracle(batch):
     run = contraction(circ, words, cap=7, batch=batch)
     assert run.n_slices >= 8
     got = run.amplitudes()
-    assert rel_err(got, ref) <= 1e-5
+    assert_close(got, ref, 1e-5)
     # the sum over slices is not any single slice: splitting the range and
     # adding into one buffer is bit-identical to a single call
     amps = run.new_amplitudes()
@@ -74,7 +74,7 @@ def test_open_legs_against_statevector():
             for t, q in enumerate(opens):
                 word = (word & ~(1 << q)) | (((j >> t) & 1) << q)
             ref[i, j] = statevector.amplitudes_from_state(psi, [word])[0]
-    assert rel_err(got, ref) <= 1e-5
+    assert_close(got, ref, 1e-5)
     run.close()
 
 
@@ -89,7 +89,7 @@ def test_duplicates_and_determinism():
     a2 = run.amplitudes()
     assert np.array_equal(a1, a2)
     ref = statevector.amplitudes(circ, words)
-    assert rel_err(a1, ref) <= 1e-5
+    assert_close(a1, ref, 1e-5)
     assert np.array_equal(a1[12:17], a1[:5])
     run.close()
 
@@ -101,7 +101,7 @@ def test_product_state():
     say("product 2x3")
     run = contraction(circ, words)
     got = run.amplitudes()
-    assert rel_err(got, closed_forms.product_amplitudes(circ, words)) <= 1e-6
+    assert_close(got, closed_forms.product_amplitudes(circ, words), 1e-6)
     run.close()
 
 
@@ -129,7 +129,7 @@ def test_permutation_circuit_c2_size():
     run = contraction(circ, words, cap=28, batch=2, trials=4)
     got = run.amplitudes()
     ref = closed_forms.permutation_amplitudes(circ, words)
-    assert rel_err(got, ref) <= 1e-5
+    assert_close(got, ref, 1e-5)
     run.close()
 
 
@@ -148,7 +148,7 @@ def test_c2_full_config_against_stored_oracle():
     say("C2 full config, cap 28, k=4096, batch 4")
     run = contraction(circ, words, cap=28, batch=4, trials=4)
     got = run.amplitudes()[idx]
-    assert rel_err(got, ref) <= 1e-5
+    assert_close(got, ref, 1e-5)
     n = 30
     assert abs((np.ldexp(np.mean(np.abs(got) ** 2), n) - 1) - (np.ldexp(np.mean(np.abs(ref) ** 2), n) - 1)) <= 1e-4
     run.close()
@@ -190,7 +190,7 @@ def test_key_chunks_match_single_pass(precision):
             full.append(word)
     ref = statevector.amplitudes_from_state(psi, full)
     got = b.cpu().numpy()
-    assert rel_err(got[..., 0] + 1j * got[..., 1], ref) <= (3e-3 if precision == "chalf" else 1e-5)
+    assert_close(got[..., 0] + 1j * got[..., 1], ref, (3e-3 if precision == "chalf" else 1e-5))
     one.close()
     many.close()
 
@@ -213,8 +213,8 @@ def test_fan_out_tiles_against_statevector(grid, depth, cap, k, seed, precision)
     run = contraction(circ, words, cap=cap, batch=2, precision=precision, trials=4)
     assert run.info.n_fan_nodes >= 1
     bar = 3e-3 if precision == "chalf" else 1e-5
-    assert rel_err(run.amplitudes(), ref) <= bar
+    assert_close(run.amplitudes(), ref, bar)
     run.autotune(reps=1, cache_path="")
-    assert rel_err(run.amplitudes(), ref) <= bar
+    assert_close(run.amplitudes(), ref, bar)
     assert abs(run.xeb() - oxeb.linear_xeb(ref, n)) <= 1e-4
     run.close()

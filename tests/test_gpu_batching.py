@@ -12,7 +12,7 @@ import os
 import numpy as np
 import pytest
 
-from gpu_util import rel_err, require_gpu, say
+from gpu_util import assert_close, rel_err, require_gpu, say
 from oracle import statevector, xeb as oxeb
 from workload import GridSpec, random_circuit, uniform_bitstrings
 
@@ -64,14 +64,14 @@ def test_autotune_keeps_parity_and_writes_cache(tmp_path):
     path = str(tmp_path / "tune.json")
     run.autotune(reps=2, cache_path=path)
     got = run.amplitudes()
-    assert rel_err(got, ref) <= 1e-5
+    assert_close(got, ref, 1e-5)
     if run.info.n_mfma_nodes:
         table = json.load(open(path))
         assert table and all(isinstance(v, int) for v in table.values())
         # a second plan reads its choices from the cache
         run2, _ = build(circ, words, 12, 4)
         run2.autotune(reps=2, cache_path=path)
-        assert rel_err(run2.amplitudes(), ref) <= 1e-5
+        assert_close(run2.amplitudes(), ref, 1e-5)
         run2.close()
     run.close()
 
@@ -100,7 +100,7 @@ def test_queue_of_uneven_plans():
         for i, (a, (ref, n)) in enumerate(zip(amps, refs)):
             c = a.cpu().numpy()
             c = c[..., 0, 0] + 1j * c[..., 0, 1]
-            assert rel_err(c, ref) <= 1e-5
+            assert_close(c, ref, 1e-5)
             assert abs(xs[i] - oxeb.linear_xeb(ref, n)) <= 1e-4
         snap = [a.cpu().numpy() for a in amps]
         if first is None:

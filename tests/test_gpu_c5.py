@@ -1,19 +1,68 @@
-"""The uneven batch through one queue: the circuits of the seeded uneven
-batch with at most 25 qubits (10 of the 32: 20-25 qubits, depth 10-16,
-256-4096 bitstrings), with their stored plans, contracted in complex-half as
-one captured queue, against the oracle's state vector; every replay of the
-queue must be bit-identical to the first."""
+"""The uneven batch of 32 seeded circuits (20-36 qubits, depth 10-16,
+256-4096 bitstrings) with their stored plans, in complex-half (the
+workload's precision), against the oracle:
+
+* the 10 circuits of at most 25 qubits, contracted as one captured queue,
+  against the oracle's state vector computed here; every replay of the
+  queue is bit-identical to the first;
+* the 6 circuits of 26-30 qubits, as a second queue, against the stored
+  state-vector amplitudes of tests/golden/c5_sv.json (oracle.sv_native);
+* the 16 circuits of 31-36 qubits, beyond any state vector: each stored
+  plan is bound to its random circuit, then the leaves of the permutation
+  circuit of the same grid and depth (same network structure) are swapped
+  in with matnc_plan_set_tensor.  Exactly one slice -- the trajectory's --
+  contributes, and it must give the exact amplitudes
+  (oracle.closed_forms), whose XEB is 0; a neighbouring slice must give
+  zero.
+  Swapping the random leaves back must reproduce the first result bit for
+  bit.
+
+Bars: ||a - a_ref|| / ||a_ref|| <= 3e-3, max |a - a_ref| / rms <= 3e-2,
+|XEB - XEB_ref| <= 1e-4.
+"""
+
+import json
+import os
 
 import numpy as np
 import pytest
 
-from gpu_util import rel_err, require_gpu, say
-from oracle import sv_native, xeb as oxeb
+from gpu_util import assert_close, require_gpu, say
+from oracle import closed_forms, sv_native, xeb as oxeb
+from workload import permutation_circuit
 
 pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TOL = 3e-3
 
 
-def test_uneven_queue_against_statevector():
+def _plan_spec(api, e):
+    return api.PlanSpec([tuple(x) for x in e["pairs"]], e["sliced"], (), e["cap"])
+
+
+def _queue_against(runs, refs, stream):
+    from paper_2212_04749_amd import api
+    q = api.Queue(runs)
+    amps, xeb = q.execute()
+    stream.synchronize()
+    first = [a.cpu().numpy() for a in amps]
+    xs = xeb.cpu().numpy()
+    for (name, n, ref), a, x in zip(refs, first, xs):
+        got = a[:, 0, 0] + 1j * a[:, 0, 1]
+        e = assert_close(got, ref, TOL, name)
+        xe = abs(x - oxeb.linear_xeb(ref, n))
+        say(f"{name}: {n} qubits, rel err {e:.2e}, xeb {x:.4f}, xeb err {xe:.2e}")
+        assert xe <= 1e-4, name
+    for rep in range(2):
+        q.execute(amps, xeb)
+        stream.synchronize()
+        assert all(np.array_equal(f, a.cpu().numpy()) for f, a in zip(first, amps)), f"replay {rep}"
+    q.close()
+    for r in runs:
+        r.close()
+
+
+def test_uneven_queue_up_to_25_qubits_against_statevector():
     torch = require_gpu()
     from paper_2212_04749_amd import api
     from paper_2212_04749_amd.circuit_tn import build_network
@@ -25,28 +74,158 @@ def test_uneven_queue_against_statevector():
     for w in uneven_batch_c5():
         if w.n_qubits > 25:
             continue
-        e = plans[w.name]
         net = build_network(w.circuit())
-        spec = api.PlanSpec([tuple(x) for x in e["pairs"]], e["sliced"], (), e["cap"])
-        runs.append(api.Contraction(net, spec, w.bitstrings(), precision="chalf", stream=stream))
+        runs.append(api.Contraction(net, _plan_spec(api, plans[w.name]), w.bitstrings(), precision="chalf",
+                                    stream=stream))
         refs.append((w.name, w.n_qubits, sv_native.amplitudes(w.circuit(), w.bitstrings())))
     assert len(runs) == 10
-    say(f"uneven queue of {len(runs)} circuits")
-    q = api.Queue(runs)
-    amps, xeb = q.execute()
-    stream.synchronize()
-    first = [a.cpu().numpy() for a in amps]
-    xs = xeb.cpu().numpy()
-    for (name, n, ref), a, x in zip(refs, first, xs):
-        got = a[:, 0, 0] + 1j * a[:, 0, 1]
-        e = rel_err(got, ref)
-        say(f"{name}: {n} qubits, rel err {e:.2e}, xeb {x:.4f}")
-        assert e <= 3e-3, name
-        assert abs(x - oxeb.linear_xeb(ref, n)) <= 1e-4, name
-    for rep in range(2):
-        q.execute(amps, xeb)
-        stream.synchronize()
-        assert all(np.array_equal(f, a.cpu().numpy()) for f, a in zip(first, amps)), f"replay {rep}"
-    q.close()
-    for r in runs:
+    say(f"uneven queue of {len(runs)} circuits (<= 25 qubits)")
+    _queue_against(runs, refs, stream)
+
+
+def test_uneven_queue_26_to_30_qubits_against_stored_statevector():
+    torch = require_gpu()
+    from paper_2212_04749_amd import api
+    from paper_2212_04749_amd.circuit_tn import build_network
+    from paper_2212_04749_amd.plans import make_c5
+    from workload.configs import uneven_batch_c5
+    plans = make_c5.load()
+    g = json.load(open(os.path.join(GOLDEN, "c5_sv.json")))["circuits"]
+    stream = torch.cuda.Stream()
+    runs, refs = [], []
+    for w in uneven_batch_c5():
+        if not 26 <= w.n_qubits <= 30:
+            continue
+        words = w.bitstrings()
+        assert [str(int(x)) for x in words] == g[w.name]["words"], w.name
+        ref = np.array([complex(a, b) for a, b in g[w.name]["amps"]])
+        net = build_network(w.circuit())
+        runs.append(api.Contraction(net, _plan_spec(api, plans[w.name]), words, precision="chalf", stream=stream))
+        refs.append((w.name, w.n_qubits, ref))
+    assert len(runs) == 6
+    say(f"uneven queue of {len(runs)} circuits (26..30 qubits)")
+    _queue_against(runs, refs, stream)
+
+
+def _trajectory_slice(net, sliced, traj):
+    """Slice id whose bits are the trajectory's values on the sliced wires
+    (tensor t of the fused network is the t-th two-qubit gate; its first two
+    indices are that gate's output wires)."""
+    sigma = 0
+    for j, bond in enumerate(sliced):
+        for t, ix in enumerate(net.indices[:len(traj)]):
+            if bond in ix[:2]:
+                (qa, va), (qb, vb) = traj[t]
+                sigma |= (va if bond == ix[0] else vb) << j
+                break
+        else:
+            raise AssertionError("sliced index is not a two-qubit gate output wire")
+    return sigma
+
+
+def _uneven_large():
+    from workload.configs import uneven_batch_c5
+    return [w for w in uneven_batch_c5() if w.n_qubits > 30]
+
+
+@pytest.mark.parametrize("name", [w.name for w in _uneven_large()])
+def test_uneven_31_to_36_qubits_permutation_leaves(name):
+    require_gpu()
+    from paper_2212_04749_amd import api
+    from paper_2212_04749_amd.circuit_tn import build_network
+    from paper_2212_04749_amd.plans import make_c5
+    w = next(x for x in _uneven_large() if x.name == name)
+    e = make_c5.load()[name]
+    words = w.bitstrings()
+    net = build_network(w.circuit())
+    pcirc = permutation_circuit(w.grid, w.depth, 700 + int(name.split(".")[1]))
+    pnet = build_network(pcirc)
+    assert pnet.indices == net.indices and pnet.output_index == net.output_index
+    run = api.Contraction(net, _plan_spec(api, e), words, precision="chalf")
+    n_sl = run.n_slices
+    sigma = _trajectory_slice(pnet, e["sliced"], closed_forms.permutation_trajectory(pcirc))
+    say(f"{name}: {w.n_qubits} qubits, depth {w.depth}, {len(words)} bitstrings, {n_sl} slices, "
+        f"{run.info.n_chunks} chunks, trajectory slice {sigma}")
+    # the random circuit's contribution of that slice, kept to check the swap back
+    a_rand = run.execute(None, sigma, sigma + 1)
+    run.synchronize()
+    first = a_rand.cpu().numpy()
+    for t, x in enumerate(pnet.tensors):
+        run.set_tensor(t, x)
+    amps = run.execute(None, sigma, sigma + 1)
+    xeb = run.xeb(amps)
+    a = amps.cpu().numpy()
+    got = a[:, 0, 0] + 1j * a[:, 0, 1]
+    ref = closed_forms.permutation_amplitudes(pcirc, words)
+    assert np.allclose(np.abs(ref), 2.0 ** (-w.n_qubits / 2), rtol=1e-12)
+    err = assert_close(got, ref, TOL, name)
+    say(f"{name}: permutation leaves, rel err {err:.2e}, xeb {xeb:.2e}")
+    # the exact XEB is 0 (every |a|^2 = 2^-n); with all |a| equal, an error
+    # of rms r relative to |a| moves it by at most 2 r + r^2
+    assert abs(xeb - oxeb.linear_xeb(got, w.n_qubits)) <= 1e-12
+    assert abs(xeb) <= 2 * err + err * err + 1e-12
+    if n_sl > 1:
+        other = sigma ^ 1
+        a2 = run.execute(None, other, other + 1)
+        run.synchronize()
+        assert np.max(np.abs(a2.cpu().numpy())) <= 1e-6 * 2.0 ** (-w.n_qubits / 2)
+    for t, x in enumerate(net.tensors):
+        run.set_tensor(t, x)
+    again = run.execute(None, sigma, sigma + 1)
+    run.synchronize()
+    assert np.array_equal(again.cpu().numpy(), first), "leaves swapped back do not reproduce the first result"
+    run.close()
+
+
+def test_shared_arena_queue_matches_separate_workspaces():
+    # the 16 circuits of at most 30 qubits as one queue bound to ONE
+    # workspace (static regions side by side, one shared arena) against the
+    # same queue with a workspace per plan: identical amplitudes and XEB,
+    # bit for bit; then each plan executed on its own after the queue (its
+    # stem cache was overwritten by the others) gives its queue result again
+    torch = require_gpu()
+    from paper_2212_04749_amd import api, binding as B
+    from paper_2212_04749_amd.circuit_tn import build_network
+    from paper_2212_04749_amd.plans import make_c5
+    from workload.configs import uneven_batch_c5
+    plans = make_c5.load()
+    ws = [w for w in uneven_batch_c5() if w.n_qubits <= 30]
+    assert len(ws) == 16
+    nets = [build_network(w.circuit()) for w in ws]
+    s1 = torch.cuda.Stream()
+    sep = [api.Contraction(n, _plan_spec(api, plans[w.name]), w.bitstrings(), precision="chalf", stream=s1)
+           for w, n in zip(ws, nets)]
+    q1 = api.Queue(sep)
+    a1, x1 = q1.execute()
+    s1.synchronize()
+    ref = [a.cpu().numpy() for a in a1]
+    xref = x1.cpu().numpy()
+    total_sep = sum(int(r.info.workspace_bytes) for r in sep)
+    q1.close()
+    for r in sep:
+        r.close()
+    del a1, x1
+    torch.cuda.empty_cache()
+    s2 = torch.cuda.Stream()
+    shared = [api.Contraction(n, _plan_spec(api, plans[w.name]), w.bitstrings(), precision="chalf", stream=s2,
+                              bind=False) for w, n in zip(ws, nets)]
+    q2 = api.Queue(shared, shared=True)
+    need = B.matnc_queue_workspace_bytes(q2._q)
+    say(f"shared-arena queue: {need / 2**30:.2f} GiB against {total_sep / 2**30:.2f} GiB in separate workspaces")
+    assert need < total_sep
+    a2, x2 = q2.execute()
+    s2.synchronize()
+    for w, r, a in zip(ws, ref, a2):
+        assert np.array_equal(a.cpu().numpy(), r), w.name
+    assert np.array_equal(x2.cpu().numpy(), xref)
+    # replay, then each plan alone (recomputing its stem cache in the arena)
+    q2.execute(a2, x2)
+    s2.synchronize()
+    assert all(np.array_equal(a.cpu().numpy(), r) for a, r in zip(a2, ref))
+    for w, run, r in zip(ws, shared, ref):
+        alone = run.execute()
+        run.synchronize()
+        assert np.array_equal(alone.cpu().numpy(), r), f"{w.name} alone after the queue"
+    q2.close()
+    for r in shared:
         r.close()

@@ -102,6 +102,14 @@ def test_error_paths():
         B.matnc_execute(p, 0, 1, 0x1000)
     assert e.value.code == B.MATNC_E_STATE
     assert "bind" in B.matnc_last_error()
+    # set_tensor: tensor id out of range; a valid id on an unbound plan only
+    # replaces the host copy (uploaded at bind)
+    with pytest.raises(B.MatncError) as e:
+        B.matnc_plan_set_tensor(p, len(net.tensors), np.zeros(32))
+    assert e.value.code == B.MATNC_E_INVALID
+    B.matnc_plan_set_tensor(p, 0, api.tensor_array(net.tensors[0]))
+    with pytest.raises(ValueError):
+        B.matnc_plan_set_tensor(p, 0, np.zeros(3))
     B.matnc_plan_destroy(p)
     # network: bond index on three tensors
     with pytest.raises(B.MatncError) as e:
@@ -245,3 +253,26 @@ def test_c_program_uses_the_abi(tmp_path):
     assert "cmac_single 2.0 cmac_multi 8.0" in out
     assert f"bad tree rc {B.MATNC_E_INVALID} (invalid) message present" in out
     assert f"execute before bind rc {B.MATNC_E_STATE}" in out
+
+
+def test_queue_workspace_is_one_arena_plus_static_regions():
+    # plans of a queue share one arena: the queue needs more than its largest
+    # plan (every static region) but less than all plans side by side
+    ps, hs = [], []
+    for seed in (21, 22, 23):
+        circ = random_circuit(GridSpec(3, 4), 8, seed)
+        net, pl, h, p = _plan(circ, uniform_bitstrings(12, 40, seed + 100), cap=8)
+        ps.append(p)
+        hs.append(h)
+    q = B.matnc_queue_create(ps)
+    need = B.matnc_queue_workspace_bytes(q)
+    sizes = [int(B.matnc_plan_info(p).workspace_bytes) for p in ps]
+    assert max(sizes) < need < sum(sizes)
+    with pytest.raises(B.MatncError) as e:
+        B.matnc_queue_bind(q, 0x1000, need - 256, 0)
+    assert e.value.code == B.MATNC_E_NOMEM
+    B.matnc_queue_destroy(q)
+    for p in ps:
+        B.matnc_plan_destroy(p)
+    for h in hs:
+        B.matnc_network_destroy(h)

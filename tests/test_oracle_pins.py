@@ -226,3 +226,76 @@ def test_permutation_trajectory_selects_one_slice():
                     assert abs(part - ref[i]) < 1e-14
                 else:
                     assert abs(part) < 1e-15
+
+
+# --- Eq. (2) fidelity estimates (the oracle's maximum likelihood and the
+# library's analysis, two independent methods) ---------------------------
+
+def _eq2_samples(fidelity, k, seed):
+    # Eq. (2) is the mixture (1 - F) e^{-x} + F x e^{-x}: Exp(1) with
+    # probability 1 - F, Gamma(2, 1) with probability F
+    rng = np.random.default_rng(seed)
+    pick = rng.random(k) < fidelity
+    return np.where(pick, rng.gamma(2.0, 1.0, k), rng.exponential(1.0, k))
+
+
+@pytest.mark.parametrize("fidelity", [0.0, 0.3, 1.0])
+def test_mle_fidelity_recovers_eq2_mixtures(fidelity):
+    from oracle import xeb as oxeb
+    k = 200_000
+    x = _eq2_samples(fidelity, k, 91)
+    f = oxeb.mle_fidelity(x)
+    sigma = np.sqrt((1 + 2 * fidelity - fidelity ** 2) / k)  # of the linear estimate, larger than the MLE's
+    assert abs(f - fidelity) <= 5 * sigma
+    assert abs((x.mean() - 1) - fidelity) <= 5 * sigma
+
+
+def test_mle_fidelity_is_the_likelihood_argmax():
+    # brute force: the maximiser of sum log(F x + 1 - F) on a fine grid
+    from oracle import xeb as oxeb
+    x = _eq2_samples(0.4, 3000, 92)
+    grid = np.linspace(0.0, 1.0, 20001)
+    ll = [np.sum(np.log(f * x + 1 - f)) for f in grid]
+    assert abs(oxeb.mle_fidelity(x) - grid[int(np.argmax(ll))]) <= 1e-4
+    # the boundaries: all x below 1 pulls F to 0, all above 1 to 1
+    assert oxeb.mle_fidelity(np.full(10, 0.5)) == 0.0
+    assert oxeb.mle_fidelity(np.full(10, 3.0)) == 1.0
+
+
+def test_density_of_eq2_integrates_to_one_with_mean_one_plus_f():
+    from oracle import xeb as oxeb
+    x = np.linspace(0, 60, 600001)
+    for f in (0.0, 0.25, 1.0):
+        p = oxeb.porter_thomas_density(x, f)
+        assert abs(np.trapezoid(p, x) - 1) < 1e-8
+        assert abs(np.trapezoid(x * p, x) - (1 + f)) < 1e-8
+
+
+def test_library_fit_matches_oracle_fit():
+    # the library's Newton fit against the oracle's bisection, same samples
+    from oracle import xeb as oxeb
+    from paper_2212_04749_amd import analysis
+    for f, seed in ((0.0, 93), (0.05, 94), (0.5, 95), (1.0, 96)):
+        x = _eq2_samples(f, 5000, seed)
+        assert abs(analysis.fit_fidelity(x) - oxeb.mle_fidelity(x)) <= 1e-9
+
+
+def test_probabilities_match_amplitudes_and_sum_to_one():
+    from oracle import statevector
+    from workload import GridSpec, random_circuit, uniform_bitstrings
+    circ = random_circuit(GridSpec(2, 3), 6, 97)
+    p = statevector.probabilities(circ)
+    assert abs(p.sum() - 1) < 1e-12
+    words = uniform_bitstrings(6, 20, 98)
+    a = statevector.amplitudes(circ, words)
+    assert np.allclose(p[words.astype(np.int64)], np.abs(a) ** 2, atol=1e-15)
+
+
+def test_mixture_sampler_follows_its_distribution():
+    from workload import sample_mixture
+    p = np.array([0.5, 0.25, 0.125, 0.125])
+    w = sample_mixture(p, 100_000, 1.0, 99)
+    freq = np.bincount(w.astype(np.int64), minlength=4) / w.size
+    assert np.allclose(freq, p, atol=0.01)
+    w0 = sample_mixture(p, 100_000, 0.0, 99)
+    assert np.allclose(np.bincount(w0.astype(np.int64), minlength=4) / w0.size, 0.25, atol=0.01)
