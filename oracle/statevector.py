@@ -40,3 +40,12 @@ def amplitudes_from_state(psi: np.ndarray, words) -> np.ndarray:
 
 def amplitudes(circ: dict, words) -> np.ndarray:
     return amplitudes_from_state(final_state(circ), words)
+
+
+def probabilities(circ: dict) -> np.ndarray:
+    """|<b|psi>|^2 for every bitstring b, indexed by the packed word
+    (bit q = qubit q, so qubit n-1 is the most significant)."""
+    psi = final_state(circ)
+    n = psi.ndim
+    flat = np.transpose(psi, tuple(range(n - 1, -1, -1))).reshape(-1)
+    return (flat.real * flat.real + flat.imag * flat.imag).astype(np.float64)

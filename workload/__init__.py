@@ -18,5 +18,5 @@ from .rqc import (  # noqa: F401
     circuit_to_json,
     circuit_from_json,
 )
-from .bitstrings import uniform_bitstrings, bits_to_u64, u64_to_bits  # noqa: F401
+from .bitstrings import uniform_bitstrings, bits_to_u64, u64_to_bits, sample_mixture  # noqa: F401
 from .configs import CONFIGS, sub_instance_c4, uneven_batch_c5  # noqa: F401

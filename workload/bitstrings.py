@@ -36,3 +36,21 @@ def subset(words: np.ndarray, m: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     idx = np.sort(rng.choice(len(words), size=min(m, len(words)), replace=False))
     return idx
+
+
+def sample_mixture(probs: np.ndarray, k: int, fidelity: float, seed: int) -> np.ndarray:
+    """k bitstrings (packed uint64, bit q = qubit q) from the mixture that
+    draws each one, independently, from the distribution ``probs`` (indexed
+    by the packed bitstring) with probability ``fidelity`` and uniformly
+    otherwise -- the model of a noisy device's samples behind Eq. (2)."""
+    probs = np.asarray(probs, dtype=np.float64).reshape(-1)
+    size = probs.size
+    if size & (size - 1) or not 0.0 <= fidelity <= 1.0:
+        raise ValueError("probs must have 2^n entries and fidelity must be in [0, 1]")
+    rng = np.random.default_rng(seed)
+    from_p = rng.random(k) < fidelity
+    out = rng.integers(0, size, size=k, dtype=np.uint64)
+    n_p = int(from_p.sum())
+    if n_p:
+        out[from_p] = rng.choice(size, size=n_p, p=probs / probs.sum()).astype(np.uint64)
+    return out
