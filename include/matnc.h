@@ -128,6 +128,39 @@ int matnc_plan_create(matnc_network net, const int *pairs, int n_sliced,
                       int max_rank, int slice_batch, size_t memory_budget,
                       matnc_plan *out);
 
+/*
+ * matnc_plan_create_ex -- matnc_plan_create with its tuning choices in a
+ * struct (zero-initialise it, then set the fields):
+ *   slice_batch, memory_budget   as in matnc_plan_create
+ *   half_extra                   complex-half plans: besides the tensors of
+ *                                the twig (reuse width >= a quarter of the
+ *                                distinct bitstrings), the number of other
+ *                                intermediates stored in FP16 -- those whose
+ *                                steps carry the most estimated FP32 time,
+ *                                which then run on the FP16 MFMA kernels.
+ *                                Each adds one FP16 rounding (relative rms
+ *                                about 2^-11/sqrt(3)) common to every
+ *                                amplitude; -1 = library default (8 for
+ *                                batches of at least 4096 amplitudes, k *
+ *                                2^n_open, else 0: the linear XEB of K
+ *                                amplitudes moves by about a few times the
+ *                                relative error over sqrt(K)), 0 = the twig
+ *                                only.  Ignored for MATNC_C64.
+ * Errors: as matnc_plan_create; MATNC_E_INVALID for a null opts or
+ * half_extra < -1.
+ */
+typedef struct {
+  int slice_batch;
+  size_t memory_budget;
+  int half_extra;
+} matnc_plan_options_t;
+
+int matnc_plan_create_ex(matnc_network net, const int *pairs, int n_sliced,
+                         const int *sliced_ids, int n_open, const int *open_qubits,
+                         int64_t k, const uint64_t *bitstrings, int precision,
+                         int max_rank, const matnc_plan_options_t *opts,
+                         matnc_plan *out);
+
 typedef struct {
   double cmac_single;       /* S: complex MACs of one amplitude, one slice   */
   double cmac_multi;        /* S_k: complex MACs of the batch, one slice     */
@@ -146,14 +179,21 @@ typedef struct {
   size_t cache_bytes;       /* part of it holding slice-invariant tensors    */
   int n_chunks;             /* key chunks the bitstrings are processed in    */
   int n_fan_nodes;          /* MFMA steps run as fan-out tiles               */
+  int n_half_nodes;         /* complex-half: intermediates stored in FP16    */
 } matnc_plan_info_t;
 
 int matnc_plan_info(matnc_plan plan, matnc_plan_info_t *info);
 
 /*
  * matnc_plan_set_tensor -- replace the data of tensor t (same index list);
- * complex128 as in matnc_network_create.  Invalidates the slice-invariant
- * cache; takes effect at the next execute.  Errors: MATNC_E_INVALID.
+ * complex128 as in matnc_network_create, 2 * 2^rank(t) doubles.  The
+ * network of a circuit (Supplementary Sec. II) depends on the gates only
+ * through its numbers, so circuits with the same layout (another seed, the
+ * permutation circuits used for exact checks) share one plan.  Bound plans
+ * upload the new leaf variants at once (and wait for that copy); the
+ * slice-invariant cache is invalidated and the change takes effect at the
+ * next execute, through the same captured graphs.
+ * Errors: MATNC_E_INVALID (null data, t out of range), MATNC_E_HIP.
  */
 int matnc_plan_set_tensor(matnc_plan plan, int t, const double *data_c128);
 
@@ -161,7 +201,9 @@ int matnc_plan_set_tensor(matnc_plan plan, int t, const double *data_c128);
  * matnc_plan_bind -- attach the caller's device workspace (at least
  * workspace_bytes, 256-byte aligned) and HIP stream (hipStream_t, may be
  * NULL for the null stream), upload leaf variants, gather maps and offset
- * tables.  The per-batch launch sequence of each chunk is captured as a HIP
+ * tables.  The workspace holds the static memory plan of the reuse tree
+ * (Supplementary Sec. III.C: with the reuse tree fixed before running, the
+ * place and lifetime of every intermediate is known in advance).  The per-batch launch sequence of each chunk is captured as a HIP
  * graph on the first execute over a full batch (non-null stream only) and
  * replayed for every later full batch into the same amplitude buffer.
  * The workspace must stay allocated until the plan is destroyed or re-bound.
@@ -173,7 +215,10 @@ int matnc_plan_bind(matnc_plan plan, void *dev_workspace, size_t bytes, void *hi
  * matnc_execute -- contract slices [slice_begin, slice_end) and ADD their
  * contributions into amps_dev (complex128, [k][2^n_open]) in FP64, one
  * slice after another in increasing slice id (so any split of a slice range
- * into calls gives bit-identical results).  Slice-invariant intermediates
+ * into calls gives bit-identical results).  Each slice is the multi-
+ * amplitude contraction of the main text (every intermediate computed once
+ * per distinct projection of the batch, Eq. (1)); the amplitude is the sum
+ * over slices (Supplementary Sec. IV.B).  Slice-invariant intermediates
  * are computed on the first call after bind/set_tensor and kept (stem
  * cache).  With several key chunks, the chunks run one after another: each
  * first computes its own instances of the invariant nodes wider than one
@@ -239,8 +284,11 @@ int matnc_plan_profile(matnc_plan plan, int64_t slice_begin, int nb, float *time
 
 /*
  * Uneven batches: several bound plans (each with its own workspace and
- * circuit) executed over all of their slices as one queue, with one FP64
- * amplitude buffer and one XEB slot per plan.
+ * circuit, or all on one workspace through matnc_queue_bind) executed over
+ * all of their slices as one queue, with one FP64 amplitude buffer and one
+ * XEB slot per plan -- contractions of very different sizes batched into
+ * one launch sequence, as the tensor-size-dependent parallelisation of
+ * Supplementary Sec. V batches many small contractions.
  *   matnc_queue_execute(q, amps_dev[n], xeb_dev[n]) contracts every slice
  *   of every plan (adding into amps_dev[i]) and writes XEB of plan i to
  *   xeb_dev[i].  All plans must be bound to the same (non-null) stream.  The
@@ -251,6 +299,27 @@ int matnc_plan_profile(matnc_plan plan, int64_t slice_begin, int nb, float *time
 int matnc_queue_create(int n_plans, const matnc_plan *plans, matnc_queue *out);
 int matnc_queue_execute(matnc_queue q, double *const *amps_dev, double *xeb_dev);
 int matnc_queue_destroy(matnc_queue q);
+
+/*
+ * matnc_queue_workspace_bytes -- device workspace matnc_queue_bind needs:
+ * the static regions of all plans (leaf data, gather maps, offset tables,
+ * scale slots) side by side, then ONE arena for the intermediates, as large
+ * as the largest plan's -- the plans of a queue run one after another, so
+ * their intermediates (stem caches included) never need to coexist.
+ *
+ * matnc_queue_bind -- bind every plan of the queue to one caller workspace
+ * (256-byte aligned, at least matnc_queue_workspace_bytes) and one stream,
+ * replacing each plan's own binding (so a queue of circuits of uneven size
+ * fits wherever its largest member fits).  The next matnc_queue_execute
+ * captures the whole queue as one graph.  A plan may still be executed on
+ * its own afterwards: it recomputes its slice-invariant tensors whenever
+ * another plan of the queue has used the arena since.  The workspace must
+ * stay allocated while the plans are bound to it.
+ * Errors: MATNC_E_NOMEM (workspace too small), MATNC_E_INVALID (misaligned,
+ * a plan listed twice), MATNC_E_HIP.
+ */
+int matnc_queue_workspace_bytes(matnc_queue q, size_t *out);
+int matnc_queue_bind(matnc_queue q, void *dev_workspace, size_t bytes, void *hip_stream);
 
 /*
  * matnc_contract -- one pairwise contraction with bit-permuted layouts

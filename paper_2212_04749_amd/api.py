@@ -52,9 +52,13 @@ class Contraction:
     """One network + plan bound to a torch workspace and stream."""
 
     def __init__(self, net: TensorNetwork, spec: PlanSpec, words, precision: str = "c64",
-                 slice_batch: int = 1, stream=None, device: str = "cuda", memory_budget: Optional[int] = None):
+                 slice_batch: int = 1, stream=None, device: str = "cuda", memory_budget: Optional[int] = None,
+                 half_extra: int = -1, bind: bool = True):
         """memory_budget: largest workspace in bytes (None: 90% of the device
-        memory free now); above it the bitstrings are processed in chunks."""
+        memory free now); above it the bitstrings are processed in chunks.
+        half_extra: complex-half plans, FP16-stored intermediates outside the
+        twig (-1: the library's default; see matnc_plan_create_ex).
+        bind=False: create the plan only; a Queue(shared=True) binds it."""
         import torch
 
         self.torch = torch
@@ -72,18 +76,20 @@ class Contraction:
         self._net = B.matnc_network_create(ranks, ids, data, net.n_qubits, net.output_index)
         self._plan = None
         try:
-            self._plan = B.matnc_plan_create(self._net, spec.pairs, spec.sliced, list(spec.open_qubits),
-                                             self.words, PRECISIONS[precision], spec.cap, slice_batch,
-                                             memory_budget)
+            self._plan = B.matnc_plan_create_ex(self._net, spec.pairs, spec.sliced, list(spec.open_qubits),
+                                                self.words, PRECISIONS[precision], spec.cap, slice_batch,
+                                                memory_budget, half_extra)
             self.info = B.matnc_plan_info(self._plan)
             self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
-            # allocate on the plan's stream so that the caching allocator
-            # orders reuse of this memory after the plan's kernels
-            with torch.cuda.stream(self.stream):
-                self.workspace = torch.empty(max(256, int(self.info.workspace_bytes)), dtype=torch.uint8,
-                                             device=self.device)
-            B.matnc_plan_bind(self._plan, self.workspace.data_ptr(), self.workspace.numel(),
-                              self.stream.cuda_stream)
+            self.workspace = None
+            if bind:
+                # allocate on the plan's stream so that the caching allocator
+                # orders reuse of this memory after the plan's kernels
+                with torch.cuda.stream(self.stream):
+                    self.workspace = torch.empty(max(256, int(self.info.workspace_bytes)), dtype=torch.uint8,
+                                                 device=self.device)
+                B.matnc_plan_bind(self._plan, self.workspace.data_ptr(), self.workspace.numel(),
+                                  self.stream.cuda_stream)
         except Exception:
             self.close()
             raise
@@ -96,13 +102,13 @@ class Contraction:
     def from_circuit(cls, circ: dict, words, open_qubits: Sequence[int] = (), cap: Optional[int] = None,
                      precision: str = "c64", slice_batch: int = 1, seed: int = 0, trials: int = 32,
                      exact_slices: Optional[int] = None, stream=None, device: str = "cuda",
-                     memory_budget: Optional[int] = None):
+                     memory_budget: Optional[int] = None, half_extra: int = -1):
         net = build_network(circ)
         plan = planner.find_plan(net, words, open_qubits, cap, seed=seed, trials=trials,
                                  exact_slices=exact_slices)
         spec = PlanSpec(plan.pairs, plan.sliced, tuple(sorted(open_qubits)),
                         cap if cap is not None else 32, plan.method)
-        return cls(net, spec, words, precision, slice_batch, stream, device, memory_budget)
+        return cls(net, spec, words, precision, slice_batch, stream, device, memory_budget, half_extra)
 
     # ------------------------------------------------------------------
     def new_amplitudes(self):
@@ -178,6 +184,12 @@ class Contraction:
         return B.matnc_plan_profile(self._plan, slice_begin, nb, len(self.net.tensors) - 1)
 
     def set_tensor(self, t: int, data: np.ndarray) -> None:
+        """Replace the numbers of tensor t (same index list, so the same
+        shape); the next execute uses them."""
+        if not 0 <= t < len(self.net.tensors):
+            raise ValueError(f"tensor id {t} out of range")
+        if np.shape(data) != np.shape(self.net.tensors[t]):
+            raise ValueError(f"tensor {t} has shape {np.shape(self.net.tensors[t])}, got {np.shape(data)}")
         B.matnc_plan_set_tensor(self._plan, t, tensor_array(data))
 
     def close(self):
@@ -225,13 +237,27 @@ def contract_pair(A, Bt, C, pos, kernel: int = -1, stream=None):
 
 
 class Queue:
-    """Several bound contractions executed as one captured graph (uneven
-    batches); they must share one stream."""
+    """Several contractions executed as one captured graph (uneven batches);
+    they must share one stream.  shared=True binds them all to one workspace
+    (their static regions side by side and one arena as large as the
+    largest plan's, see matnc_queue_bind), so the runs may be created with
+    bind=False."""
 
-    def __init__(self, runs):
+    def __init__(self, runs, shared: bool = False):
+        import torch
         self.runs = list(runs)
         self._q = B.matnc_queue_create([r._plan for r in self.runs])
         self.stream = self.runs[0].stream
+        self.workspace = None
+        if shared:
+            need = B.matnc_queue_workspace_bytes(self._q)
+            dev = self.runs[0].device
+            with torch.cuda.stream(self.stream):
+                self.workspace = torch.empty(max(256, need), dtype=torch.uint8, device=dev)
+            B.matnc_queue_bind(self._q, self.workspace.data_ptr(), self.workspace.numel(), self.stream.cuda_stream)
+            for r in self.runs:
+                r.stream = self.stream
+                r.workspace = self.workspace  # keeps the shared memory alive with every run
 
     def execute(self, amps=None, xeb=None):
         """One pass of every plan; returns (list of amplitude tensors, XEB

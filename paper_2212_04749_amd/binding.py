@@ -51,6 +51,7 @@ class PlanInfo(ctypes.Structure):
         ("cache_bytes", c_size_t),
         ("n_chunks", c_int),
         ("n_fan_nodes", c_int),
+        ("n_half_nodes", c_int),
     ]
 
     def as_dict(self) -> dict:
@@ -65,7 +66,8 @@ EXPORTS = [
     "matnc_execute", "matnc_xeb", "matnc_plan_destroy", "matnc_queue_create",
     "matnc_queue_execute", "matnc_queue_destroy", "matnc_contract_scratch_bytes",
     "matnc_mfma_config_count", "matnc_contract", "matnc_plan_reset_cache", "matnc_plan_profile",
-    "matnc_plan_autotune",
+    "matnc_plan_autotune", "matnc_plan_create_ex", "matnc_queue_workspace_bytes",
+    "matnc_queue_bind",
 ]
 
 
@@ -106,6 +108,10 @@ def lib():
     L.matnc_contract.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_int, c_int, c_int,
                                  POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_int),
                                  POINTER(c_int), POINTER(c_int), c_int, c_void_p, c_size_t, c_void_p]
+    L.matnc_plan_create_ex.argtypes = [c_void_p, POINTER(c_int), c_int, POINTER(c_int), c_int, POINTER(c_int),
+                                       c_int64, POINTER(c_uint64), c_int, c_int, c_void_p, POINTER(c_void_p)]
+    L.matnc_queue_workspace_bytes.argtypes = [c_void_p, POINTER(c_size_t)]
+    L.matnc_queue_bind.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("matnc_version", "matnc_last_error", "matnc_contract_scratch_bytes",
@@ -171,6 +177,22 @@ def matnc_plan_create(net: int, pairs, sliced_ids, open_qubits, bitstrings, prec
     return out.value
 
 
+class PlanOptions(ctypes.Structure):
+    _fields_ = [("slice_batch", c_int), ("memory_budget", c_size_t), ("half_extra", c_int)]
+
+
+def matnc_plan_create_ex(net: int, pairs, sliced_ids, open_qubits, bitstrings, precision: int, max_rank: int,
+                         slice_batch: int = 1, memory_budget: int = 0, half_extra: int = -1) -> int:
+    out = c_void_p()
+    flat = [x for p in pairs for x in p]
+    words, pwords = u64_array(bitstrings)
+    opts = PlanOptions(int(slice_batch), int(memory_budget), int(half_extra))
+    check(lib().matnc_plan_create_ex(c_void_p(net), int_array(flat), len(sliced_ids), int_array(sliced_ids),
+                                     len(open_qubits), int_array(open_qubits), len(words), pwords, int(precision),
+                                     int(max_rank), ctypes.byref(opts), ctypes.byref(out)))
+    return out.value
+
+
 def matnc_plan_info(plan: int) -> PlanInfo:
     info = PlanInfo()
     check(lib().matnc_plan_info(c_void_p(plan), ctypes.byref(info)))
@@ -178,7 +200,12 @@ def matnc_plan_info(plan: int) -> PlanInfo:
 
 
 def matnc_plan_set_tensor(plan: int, t: int, data_c128) -> None:
+    """data_c128: 2 * 2^rank(t) doubles (the library reads exactly that many;
+    the caller -- api.Contraction.set_tensor -- checks the tensor's shape)."""
     data, pdata = f64_array(data_c128)
+    n = data.size // 2
+    if data.ndim != 1 or data.size != 2 * n or n < 1 or n & (n - 1):
+        raise ValueError("tensor data must be 2 * 2^rank interleaved doubles")
     check(lib().matnc_plan_set_tensor(c_void_p(plan), int(t), pdata))
 
 
@@ -208,6 +235,16 @@ def matnc_queue_create(plans) -> int:
 def matnc_queue_execute(queue: int, amps_devs, xeb_dev: int) -> None:
     arr = (c_void_p * len(amps_devs))(*[c_void_p(a) for a in amps_devs])
     check(lib().matnc_queue_execute(c_void_p(queue), arr, c_void_p(xeb_dev)))
+
+
+def matnc_queue_workspace_bytes(queue: int) -> int:
+    out = c_size_t()
+    check(lib().matnc_queue_workspace_bytes(c_void_p(queue), ctypes.byref(out)))
+    return int(out.value)
+
+
+def matnc_queue_bind(queue: int, dev_workspace: int, nbytes: int, hip_stream: int) -> None:
+    check(lib().matnc_queue_bind(c_void_p(queue), c_void_p(dev_workspace), c_size_t(nbytes), c_void_p(hip_stream)))
 
 
 def matnc_queue_destroy(queue: int) -> None:

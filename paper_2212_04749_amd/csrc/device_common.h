@@ -61,8 +61,14 @@ __device__ __forceinline__ HalfScale ldg_scale(uint64_t base, int64_t i) {
 __device__ __forceinline__ void stg_scale_e(uint64_t base, int64_t i, int32_t e) {
   gmem<int32_t>(base + (uint64_t)i * sizeof(HalfScale))[0] = e;
 }
+// The slot was cleared before the launch and only grows while it runs, so a
+// value read from it is never above the final maximum: when it already holds
+// at least mx_bits the atomic is skipped.  An instance spread over many tiles
+// or blocks (a stem tensor) would otherwise send every one of them to the
+// same address.
 __device__ __forceinline__ void max_scale_mx(uint64_t base, int64_t i, uint32_t mx_bits) {
-  gmax_u32(base + (uint64_t)i * sizeof(HalfScale) + offsetof(HalfScale, mx), mx_bits);
+  uint32_t* p = (uint32_t*)(base + (uint64_t)i * sizeof(HalfScale) + offsetof(HalfScale, mx));
+  if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < mx_bits) atomicMax(p, mx_bits);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
@@ -74,6 +80,31 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t vid, int64_t total) {
   const int64_t q = total >> 3, r = total & 7;
   const int64_t x = vid & 7, k = vid >> 3;
   return x * q + (x < r ? x : r) + k;
+}
+
+// Logical (unit, tile) of a logical tile index.  Plain steps: tiles of one
+// unit innermost.  Fan-out steps: the rows of the fan table that read one A
+// instance are adjacent (the table is grouped by A instance), and most groups
+// span two rows; pairing consecutive rows with the m tile outermost inside
+// the pair makes the two tiles that read the same A tile adjacent, so they
+// run together on one XCD and the second read hits its L2.  A bijection on
+// [0, units * tiles) (an odd last row keeps its own order).
+template <bool FAN>
+__device__ __forceinline__ void unit_tile(int64_t lt, int64_t units, int64_t tiles, int64_t& u, int64_t& t) {
+  if (!FAN) {
+    u = lt / tiles;
+    t = lt - u * tiles;
+    return;
+  }
+  const int64_t pair = lt / (2 * tiles);
+  const int64_t r = lt - pair * 2 * tiles;
+  if (2 * pair + 1 >= units) {
+    u = 2 * pair;
+    t = r;
+  } else {
+    u = 2 * pair + (r & 1);
+    t = r >> 1;
+  }
 }
 
 template <typename P>

@@ -16,6 +16,7 @@
 //  * k_slice_sum: FP64 accumulation of the root instances into the caller's
 //    amplitudes, slices added one by one in slice-id order.
 //  * k_xeb: deterministic FP64 sum of |a|^2 and the linear XEB estimate.
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -30,6 +31,29 @@ namespace matnc {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
+// An operand's staged element: an FP32 pair, or (complex-half plans, whose
+// FP32 steps may read an FP16-stored child) a half2 word converted exactly to
+// FP32 and multiplied by the instance's power of two 2^e.
+template <bool H>
+struct FStage;
+template <>
+struct FStage<false> {
+  typedef f32x2 type;
+  static __device__ __forceinline__ type load(uint64_t base, uint32_t i) { return gmem<const f32x2>(base)[i]; }
+  static __device__ __forceinline__ float2 val(type r, float) { return make_float2(r.x, r.y); }
+};
+template <>
+struct FStage<true> {
+  typedef uint32_t type;
+  static __device__ __forceinline__ type load(uint64_t base, uint32_t i) { return ldg_u32(base, i); }
+  static __device__ __forceinline__ float2 val(type r, float c) {
+    __half2 h;
+    __builtin_memcpy(&h, &r, 4);
+    const float2 v = __half22float2(h);
+    return make_float2(v.x * c, v.y * c);
+  }
+};
+
 // Tile: TM = 32*RM*WM values of m, TN = 16*RN*WN complex n, TK complex k.
 // FAN: the tile's TN columns are TN >> nbits slots of 2^nbits columns, one
 // per output instance of a fan-table row (see NodeDesc); the A tile is
@@ -38,7 +62,9 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // |component| into its scale slot (complex-half plans, whose FP32 branch
 // tensors feed FP16 steps): half-wave reductions and one LDS atomic per
 // slot column, one global atomic per slot and tile.
-template <int RM, int RN, int WM, int WN, int TK, bool FAN, bool REC = false>
+// HA, HB (complex-half plans only): A, B stored in FP16 with a per-instance
+// exponent; the output is FP32 either way.
+template <int RM, int RN, int WM, int WN, int TK, bool FAN, bool REC = false, bool HA = false, bool HB = false>
 __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
   static_assert(!REC || FAN, "maxima are recorded by fan-out tiles only");
   constexpr int NT = 64 * WM * WN;
@@ -61,6 +87,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
   __shared__ uint64_t s_bb[FAN ? TN : 1];
   __shared__ uint64_t s_cb[FAN ? TN : 1];
   __shared__ uint32_t s_mx[REC ? TN : 1];  // per-slot maxima (float bits)
+  __shared__ float s_fb[(FAN && HB) ? TN : 1];  // per-slot factor 2^e of an FP16 B
 
   const gptr<const uint32_t> tab = gmem<const uint32_t>(ws + d.tab_off);
   const cptr<const uint32_t> ctab = cmem<const uint32_t>(ws + d.tab_off);  // k-step lookups
@@ -85,10 +112,11 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
 
   for (int64_t blk = blockIdx.x; blk < units * tiles; blk += gridDim.x) {
     // logical tile order: n tiles innermost (they share the A tile), then m
-    // tiles, then instances / fan rows; each XCD takes a contiguous range
+    // tiles, then instances / fan rows (fan rows in pairs, see unit_tile);
+    // each XCD takes a contiguous range
     const int64_t lt = xcd_tile(blk, units * tiles);
-    const int64_t u = lt / tiles;
-    const int64_t t = lt - u * tiles;
+    int64_t u, t;
+    unit_tile<FAN>(lt, units, tiles, u, t);
     const uint32_t m0 = (uint32_t)((t / nt_count) * TM);
     const uint32_t n0 = (uint32_t)((t % nt_count) * TN);
     int64_t s, j;
@@ -105,16 +133,20 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
     const int64_t sigma = sigma0 + s;
     const int64_t ai = operand_instance(d.A, glA, j, s, sigma);
     const int64_t bi = operand_instance(d.B, glB, j, s, sigma);
-    const gptr<const f32x2> pa = gmem<const f32x2>(ws + d.A.off + ai * d.A.inst_bytes);
-    const gptr<const f32x2> pb = gmem<const f32x2>(ws + d.B.off + bi * d.B.inst_bytes);
+    const uint64_t pa = ws + d.A.off + ai * d.A.inst_bytes;
+    const uint64_t pb = ws + d.B.off + bi * d.B.inst_bytes;
     const gptr<f32x2> pc = gmem<f32x2>(ws + d.c_off + inst * d.c_inst_bytes);
+    const float ca = HA ? ldexpf(1.f, ldg_scale(ws + d.A.scale_off, ai).e) : 1.f;
+    const float cb = HB ? ldexpf(1.f, ldg_scale(ws + d.B.scale_off, bi).e) : 1.f;
     if (tid < TN) s_cn[tid] = tlook(tab + TAB_CN * kTabSize, FAN ? (tid & nmask) : n0 + tid);
     if (FAN && tid < slots) {
       // an empty slot reads slot 0's B into columns that are never stored
       const int jg = fj[tid];
-      s_bb[tid] = d.B.off + operand_instance(d.B, glB, jg < 0 ? j : jg, s, sigma) * d.B.inst_bytes;
+      const int64_t bg = operand_instance(d.B, glB, jg < 0 ? j : jg, s, sigma);
+      s_bb[tid] = d.B.off + bg * d.B.inst_bytes;
       s_cb[tid] = jg < 0 ? 0 : d.c_off + (uint64_t)(s * d.w + jg) * d.c_inst_bytes;
       if (REC) s_mx[tid] = 0u;
+      if (HB) s_fb[tid] = ldexpf(1.f, ldg_scale(ws + d.B.scale_off, bg).e);
     }
     __syncthreads();  // the column data above is read by every wave
 
@@ -128,39 +160,44 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma(NodeDesc d, uint64_t ws, 
       akk[e] = flat / TM;
       aoff[e] = tlook(tab + TAB_AM * kTabSize, m0 + amm[e]) + tab[TAB_AK * kTabSize + akk[e]];
     }
-    gptr<const f32x2> pbe[EB];  // B instance of each element (fan tiles: its slot's)
+    uint64_t pbe[EB];  // B instance of each element (fan tiles: its slot's)
+    float cbe[EB];     // and its factor (FP16 B)
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const int flat = e * NT + tid;
       bnn[e] = flat % TN;
       bkk[e] = flat / TN;
       if (FAN) {
-        const int jg = fj[bnn[e] >> d.nbits];
-        pbe[e] = gmem<const f32x2>(ws + s_bb[bnn[e] >> d.nbits]);
+        pbe[e] = ws + s_bb[bnn[e] >> d.nbits];
+        cbe[e] = HB ? s_fb[bnn[e] >> d.nbits] : 1.f;
         boff[e] = tlook(tab + TAB_BN * kTabSize, bnn[e] & nmask) + tab[TAB_BK * kTabSize + bkk[e]];
       } else {
         pbe[e] = pb;
+        cbe[e] = cb;
         boff[e] = tlook(tab + TAB_BN * kTabSize, n0 + bnn[e]) + tab[TAB_BK * kTabSize + bkk[e]];
       }
     }
-    f32x2 ra[EA], rb[EB];
+    typename FStage<HA>::type ra[EA];
+    typename FStage<HB>::type rb[EB];
     auto gload = [&](uint32_t kba, uint32_t kbb) {
 #pragma unroll
-      for (int e = 0; e < EA; ++e) ra[e] = pa[aoff[e] + kba];
+      for (int e = 0; e < EA; ++e) ra[e] = FStage<HA>::load(pa, aoff[e] + kba);
 #pragma unroll
-      for (int e = 0; e < EB; ++e) rb[e] = pbe[e][boff[e] + kbb];
+      for (int e = 0; e < EB; ++e) rb[e] = FStage<HB>::load(pbe[e], boff[e] + kbb);
     };
     auto lstore = [&](int buf) {
 #pragma unroll
       for (int e = 0; e < EA; ++e) {
-        As[buf][akk[e] * TM + amm[e]] = ra[e].x;
-        As[buf][APL + akk[e] * TM + amm[e]] = ra[e].y;
+        const float2 v = FStage<HA>::val(ra[e], ca);
+        As[buf][akk[e] * TM + amm[e]] = v.x;
+        As[buf][APL + akk[e] * TM + amm[e]] = v.y;
       }
 #pragma unroll
       for (int e = 0; e < EB; ++e) {
-        Bs[buf][bkk[e] * TN + bnn[e]] = rb[e].x;
-        Bs[buf][BPL + bkk[e] * TN + bnn[e]] = rb[e].y;
-        Bs[buf][BP2 + bkk[e] * TN + bnn[e]] = -rb[e].y;
+        const float2 v = FStage<HB>::val(rb[e], cbe[e]);
+        Bs[buf][bkk[e] * TN + bnn[e]] = v.x;
+        Bs[buf][BPL + bkk[e] * TN + bnn[e]] = v.y;
+        Bs[buf][BP2 + bkk[e] * TN + bnn[e]] = -v.y;
       }
     };
 
@@ -343,6 +380,24 @@ bool mfma_fan_config_fits(int cfg, int mbits, int nbits, int kbits, int fan_tn) 
   return (1 << c.tn_bits) == fan_tn && nbits < c.tn_bits && mbits >= c.tm_bits && kbits >= c.tk_bits;
 }
 
+template <bool FAN, bool REC, bool HA, bool HB>
+static hipError_t launch_mfma_s(const NodeDesc& d, int cfg, unsigned grid, uint64_t ws, const int64_t* sig,
+                                hipStream_t st) {
+  switch (cfg) {
+    case 0: hipLaunchKernelGGL((k_mfma<2, 1, 2, 2, 8, FAN, REC, HA, HB>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 1: hipLaunchKernelGGL((k_mfma<2, 2, 2, 2, 8, FAN, REC, HA, HB>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 2: hipLaunchKernelGGL((k_mfma<1, 1, 2, 2, 8, FAN, REC, HA, HB>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 3: hipLaunchKernelGGL((k_mfma<4, 1, 2, 2, 8, FAN, REC, HA, HB>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 4: hipLaunchKernelGGL((k_mfma<4, 2, 2, 2, 8, FAN, REC, HA, HB>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 5:
+      if (FAN) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_mfma<2, 4, 2, 2, 8, false, false, HA, HB>), dim3(grid), dim3(256), 0, st, d, ws, sig);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <bool FAN, bool REC = false>
 static hipError_t launch_mfma_t(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {
   if (d.n_inst == 0) return hipSuccess;
@@ -353,19 +408,13 @@ static hipError_t launch_mfma_t(const NodeDesc& d, int cfg, uint64_t ws, const i
   const int64_t units = FAN ? (d.n_inst / d.w) * d.n_fan : d.n_inst;
   const int64_t tiles = ((int64_t)1 << (d.mbits - c.tm_bits)) * (FAN ? 1 : ((int64_t)1 << (d.nbits - c.tn_bits)));
   const unsigned grid = grid_for(units * tiles);
-  switch (cfg) {
-    case 0: hipLaunchKernelGGL((k_mfma<2, 1, 2, 2, 8, FAN, REC>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 1: hipLaunchKernelGGL((k_mfma<2, 2, 2, 2, 8, FAN, REC>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 2: hipLaunchKernelGGL((k_mfma<1, 1, 2, 2, 8, FAN, REC>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 3: hipLaunchKernelGGL((k_mfma<4, 1, 2, 2, 8, FAN, REC>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 4: hipLaunchKernelGGL((k_mfma<4, 2, 2, 2, 8, FAN, REC>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
-    case 5:
-      if (FAN) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((k_mfma<2, 4, 2, 2, 8, false, false>), dim3(grid), dim3(256), 0, st, d, ws, sig);
-      break;
-    default: return hipErrorInvalidValue;
+  // FP16-stored operands occur only in complex-half plans
+  if (d.A.half) {
+    if (d.B.half) return launch_mfma_s<FAN, REC, true, true>(d, cfg, grid, ws, sig, st);
+    return launch_mfma_s<FAN, REC, true, false>(d, cfg, grid, ws, sig, st);
   }
-  return hipGetLastError();
+  if (d.B.half) return launch_mfma_s<FAN, REC, false, true>(d, cfg, grid, ws, sig, st);
+  return launch_mfma_s<FAN, REC, false, false>(d, cfg, grid, ws, sig, st);
 }
 
 hipError_t launch_mfma(const NodeDesc& d, int cfg, uint64_t ws, const int64_t* sig, hipStream_t st) {

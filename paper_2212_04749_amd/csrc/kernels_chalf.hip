@@ -2,12 +2,12 @@
 // exponent, FP16 MFMA with FP32 accumulation.
 //
 //  * k_mfma_h: C[m, n] = sum_k A[m, k] B[k, n] with an FP16 output, on
-//    v_mfma_f32_32x32x8f16
-//    through the real embedding [Ar Ai] x [[Br, Bi], [-Bi, Br]]: each
-//    instruction covers four complex k.  For its column m a lane supplies
-//    (Ar, Ai) of two consecutive k -- exactly two stored half2 values -- and
-//    for its row 2n + d it supplies (Br, -Bi) (d = 0) or (Bi, Br) (d = 1) of
-//    the same two k.  The products of FP16 inputs are exact in the FP32
+//    gfx950's v_mfma_f32_32x32x16_f16 through the real embedding
+//    [Ar Ai] x [[Br, Bi], [-Bi, Br]]: each instruction covers eight complex
+//    k.  For its column m a lane supplies (Ar, Ai) of four consecutive k --
+//    exactly four stored half2 values, one 16-byte LDS read -- and for its
+//    row 2n + d it supplies (Br, -Bi) (d = 0) or (Bi, Br) (d = 1) of the
+//    same four k.  The products of FP16 inputs are exact in the FP32
 //    accumulator; the output is multiplied by 2^(15 - ex), ex = ceil of
 //    log2 of the bound 2^(kbits+1) mx_A mx_B, stored as FP16 below 2^15, and
 //    its measured maximum recorded for the next step.  An operand stored in
@@ -29,7 +29,7 @@ namespace matnc {
 bool chalf_available() { return true; }
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
-typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ uint32_t h2bits(__half2 h) {
   uint32_t u;
@@ -60,7 +60,7 @@ struct AStage<false> {
   static __device__ __forceinline__ uint32_t bits(type r, float c) { return f32pair_to_h2bits(r, c); }
 };
 
-// TM = 32*RM*WM values of m, TN = 16*RN*WN complex n, TK complex k (multiple of 4)
+// TM = 32*RM*WM values of m, TN = 16*RN*WN complex n, TK complex k (multiple of 8)
 // FAN: fan-out tiles as in k_mfma (desc.h): the TN columns are slots of
 // 2^nbits columns, one per output instance sharing the A instance; every
 // slot has its own B scale, output exponent and recorded maximum.
@@ -69,22 +69,27 @@ struct AStage<false> {
 // Per-column data (C column offsets; for fan tiles each slot's output base,
 // factors and exponent) is kept in LDS, shared by the waves, rather than in
 // per-lane registers.
+// Operand staging works on quads: a thread loads four consecutive k of one m
+// (of A) or of one n (of B) and writes them to LDS as one 16-byte store.
 template <int RM, int RN, int WM, int WN, int TK, bool FAN, bool HA, bool HB>
 __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws, const int64_t* __restrict__ sig) {
   constexpr int NT = 64 * WM * WN;
   constexpr int TM = 32 * RM * WM;
   constexpr int TN = 16 * RN * WN;
-  constexpr int EA = TK * TM / NT;
-  constexpr int EB = TK * TN / NT;
-  static_assert(EA * NT == TK * TM && EB * NT == TK * TN, "tile must split evenly over threads");
-  static_assert(TK % 4 == 0, "four complex k per instruction");
-  // LDS tiles in the register layout of the MFMA operands, so that each
-  // operand is one 8-byte LDS read: As[k/2][m][k%2] holds A's half2 (re, im);
-  // Bs[k/2][n][d][k%2] holds B's column pair of the real embedding, (re, -im)
-  // for d = 0 and (im, re) for d = 1
-  constexpr int APAIR = 2 * TM + 8;  // u32 per k pair (padded)
-  __shared__ __attribute__((aligned(16))) uint32_t As[2][(TK / 2) * APAIR];
-  __shared__ __attribute__((aligned(16))) uint32_t Bs[2][(TK / 2) * TN * 4];
+  static_assert(TK % 8 == 0, "eight complex k per instruction");
+  constexpr int QA = (TK / 4) * TM;  // k quads of the A tile
+  constexpr int QB = (TK / 4) * TN;  // ... and of the B tile
+  static_assert(QA % NT == 0, "A quads must split evenly over threads");
+  static_assert(QB % NT == 0 || NT % QB == 0, "B quads must split evenly over threads, or fit in fewer");
+  constexpr int EQA = QA / NT;
+  constexpr int EQB = QB >= NT ? QB / NT : 1;
+  constexpr bool BPART = QB < NT;  // only threads tid < QB stage B
+  // LDS tiles in the register layout of the MFMA operands: As[k/4][m][k%4]
+  // holds A's half2 (re, im); Bs[k/4][n][d][k%4] holds B's column pair of
+  // the real embedding, (re, -im) for d = 0 and (im, re) for d = 1
+  constexpr int AQ = 4 * TM + 16;  // u32 per k quad (padded)
+  __shared__ __attribute__((aligned(16))) uint32_t As[2][(TK / 4) * AQ];
+  __shared__ __attribute__((aligned(16))) uint32_t Bs[2][(TK / 4) * TN * 8];
   // C offset of each of the tile's TN columns; fan-out slots: output base
   // (workspace offset, 0 = empty slot), output factor, output exponent,
   // FP32-load factor of B, recorded maximum (float bits)
@@ -118,13 +123,15 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
   const uint32_t nmask = (1u << d.nbits) - 1u;
   const int slots = FAN ? (TN >> d.nbits) : 1;
   const uint64_t scB = ws + d.B.scale_off;
+  const bool bstage = !BPART || tid < QB;
 
   for (int64_t blk = blockIdx.x; blk < units * tiles; blk += gridDim.x) {
     // logical tile order: n tiles innermost (they share the A tile), then m
-    // tiles, then instances / fan rows; each XCD takes a contiguous range
+    // tiles, then instances / fan rows (fan rows in pairs, see unit_tile);
+    // each XCD takes a contiguous range
     const int64_t lt = xcd_tile(blk, units * tiles);
-    const int64_t u = lt / tiles;
-    const int64_t t = lt - u * tiles;
+    int64_t u, t;
+    unit_tile<FAN>(lt, units, tiles, u, t);
     const uint32_t m0 = (uint32_t)((t / nt_count) * TM);
     const uint32_t n0 = (uint32_t)((t % nt_count) * TN);
     int64_t s, j;
@@ -198,58 +205,85 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
     }
     __syncthreads();  // the column data above is read by every wave
 
-    uint32_t aoff[EA], boff[EB];
-    int akk[EA], bkk[EB], amm[EA], bnn[EB];
+    // quad coordinates: A quad e of this thread covers m = amm[e], k =
+    // 4 akq[e] .. 4 akq[e] + 3 of the k step; likewise B quads over n
+    uint32_t aoff[EQA][4], boff[EQB][4];
+    int akq[EQA], amm[EQA], bkq[EQB], bnn[EQB];
 #pragma unroll
-    for (int e = 0; e < EA; ++e) {
+    for (int e = 0; e < EQA; ++e) {
       const int flat = e * NT + tid;
       amm[e] = flat % TM;
-      akk[e] = flat / TM;
-      aoff[e] = tlook(tab + TAB_AM * kTabSize, m0 + amm[e]) + tab[TAB_AK * kTabSize + akk[e]];
-    }
-    uint64_t pbe[EB];  // B instance of each element (fan tiles: its slot's)
-    float cbe[EB];
+      akq[e] = flat / TM;
+      const uint32_t om_ = tlook(tab + TAB_AM * kTabSize, m0 + amm[e]);
 #pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      const int flat = e * NT + tid;
+      for (int q = 0; q < 4; ++q) aoff[e][q] = om_ + tab[TAB_AK * kTabSize + 4 * akq[e] + q];
+    }
+    uint64_t pbe[EQB];  // B instance of each quad (fan tiles: its slot's)
+    float cbe[EQB];
+#pragma unroll
+    for (int e = 0; e < EQB; ++e) {
+      const int flat = bstage ? e * NT + tid : 0;
       bnn[e] = flat % TN;
-      bkk[e] = flat / TN;
+      bkq[e] = flat / TN;
+      uint32_t on_;
       if (FAN) {
         const int g = bnn[e] >> d.nbits;
         const int jg = fj[g];
         // an empty slot reads slot 0's B into columns that are never stored
         pbe[e] = ws + d.B.off + operand_instance(d.B, glB, jg < 0 ? j : jg, s, sigma) * d.B.inst_bytes;
         cbe[e] = s_fb[g];
-        boff[e] = tlook(tab + TAB_BN * kTabSize, bnn[e] & nmask) + tab[TAB_BK * kTabSize + bkk[e]];
+        on_ = tlook(tab + TAB_BN * kTabSize, bnn[e] & nmask);
       } else {
         pbe[e] = pb;
         cbe[e] = cb;
-        boff[e] = tlook(tab + TAB_BN * kTabSize, n0 + bnn[e]) + tab[TAB_BK * kTabSize + bkk[e]];
+        on_ = tlook(tab + TAB_BN * kTabSize, n0 + bnn[e]);
       }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) boff[e][q] = on_ + tab[TAB_BK * kTabSize + 4 * bkq[e] + q];
     }
     // raw operand words in flight (an FP32 element, or a half2 in .x); the
     // FP32 -> FP16 conversion happens when the tile is written to LDS, after
     // the MFMA work of the current step, so the loads are not waited for
     // inside the load phase
-    typename AStage<HA>::type ra[EA];
-    typename AStage<HB>::type rb[EB];
+    typename AStage<HA>::type ra[EQA][4];
+    typename AStage<HB>::type rb[EQB][4];
     auto gload = [&](uint32_t kba, uint32_t kbb) {
 #pragma unroll
-      for (int e = 0; e < EA; ++e) ra[e] = AStage<HA>::load(pa, aoff[e] + kba);
+      for (int e = 0; e < EQA; ++e)
 #pragma unroll
-      for (int e = 0; e < EB; ++e) rb[e] = AStage<HB>::load(pbe[e], boff[e] + kbb);
+        for (int q = 0; q < 4; ++q) ra[e][q] = AStage<HA>::load(pa, aoff[e][q] + kba);
+      if (bstage) {
+#pragma unroll
+        for (int e = 0; e < EQB; ++e)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) rb[e][q] = AStage<HB>::load(pbe[e], boff[e][q] + kbb);
+      }
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-      for (int e = 0; e < EA; ++e)
-        As[buf][(akk[e] >> 1) * APAIR + 2 * amm[e] + (akk[e] & 1)] = AStage<HA>::bits(ra[e], ca);
+      for (int e = 0; e < EQA; ++e) {
+        uint4 v;
+        v.x = AStage<HA>::bits(ra[e][0], ca);
+        v.y = AStage<HA>::bits(ra[e][1], ca);
+        v.z = AStage<HA>::bits(ra[e][2], ca);
+        v.w = AStage<HA>::bits(ra[e][3], ca);
+        *reinterpret_cast<uint4*>(&As[buf][akq[e] * AQ + 4 * amm[e]]) = v;
+      }
+      if (bstage) {
 #pragma unroll
-      for (int e = 0; e < EB; ++e) {
-        const uint32_t h = AStage<HB>::bits(rb[e], cbe[e]);
-        const uint32_t re = h & 0xffffu, im = h >> 16;
-        const int base = (((bkk[e] >> 1) * TN + bnn[e]) * 2) * 2 + (bkk[e] & 1);
-        Bs[buf][base] = re | ((im ^ 0x8000u) << 16);  // (Br, -Bi)
-        Bs[buf][base + 2] = im | (re << 16);           // (Bi, Br)
+        for (int e = 0; e < EQB; ++e) {
+          uint32_t lo[4], hi[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const uint32_t h = AStage<HB>::bits(rb[e][q], cbe[e]);
+            const uint32_t re = h & 0xffffu, im = h >> 16;
+            lo[q] = re | ((im ^ 0x8000u) << 16);  // (Br, -Bi)
+            hi[q] = im | (re << 16);              // (Bi, Br)
+          }
+          const int base = ((bkq[e] * TN + bnn[e]) * 2) * 4;
+          *reinterpret_cast<uint4*>(&Bs[buf][base]) = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+          *reinterpret_cast<uint4*>(&Bs[buf][base + 4]) = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+        }
       }
     };
 
@@ -285,24 +319,24 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
         }
       }
 #pragma unroll
-      for (int kq = 0; kq < TK; kq += 4) {
-        const int kp = (kq >> 1) + half;  // this lane's pair of complex k
-        halfx4 yv[RM], xv[RN];
+      for (int g = 0; g < TK / 8; ++g) {
+        const int kq = 2 * g + half;  // this lane's quad of complex k
+        halfx8 yv[RM], xv[RN];
 #pragma unroll
         for (int i = 0; i < RM; ++i) {
           const int m = (wm * RM + i) * 32 + l32;
-          yv[i] = *reinterpret_cast<const halfx4*>(&As[buf][kp * APAIR + 2 * m]);
+          yv[i] = *reinterpret_cast<const halfx8*>(&As[buf][kq * AQ + 4 * m]);
         }
 #pragma unroll
         for (int q = 0; q < RN; ++q) {
           const int n = (wn * RN + q) * 16 + ncol;
-          xv[q] = *reinterpret_cast<const halfx4*>(&Bs[buf][((kp * TN + n) * 2 + dsel) * 2]);
+          xv[q] = *reinterpret_cast<const halfx8*>(&Bs[buf][((kq * TN + n) * 2 + dsel) * 4]);
         }
 #pragma unroll
         for (int i = 0; i < RM; ++i)
 #pragma unroll
           for (int q = 0; q < RN; ++q)
-            acc[i][q] = __builtin_amdgcn_mfma_f32_32x32x8f16(xv[q], yv[i], acc[i][q], 0, 0, 0);
+            acc[i][q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xv[q], yv[i], acc[i][q], 0, 0, 0);
       }
       if (ks + 1 < ksteps) lstore(buf ^ 1);
       __syncthreads();
@@ -329,9 +363,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
         int g = 0;
         if (FAN) {
           g = nl >> d.nbits;
-          const uint64_t cb = s_cbase[g];  // uniform over the 32 lanes of a half-wave (one n)
-          live = cb != 0;
-          dst = ws + cb;
+          const uint64_t cbs = s_cbase[g];  // uniform over the 32 lanes of a half-wave (one n)
+          live = cbs != 0;
+          dst = ws + cbs;
           fo = s_f[g];
         }
         float v = 0.f;
@@ -356,7 +390,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
       if (tid < slots) {
         const int jg = fj[tid];
         if (jg >= 0) {
-          stg_scale_e(ws + d.c_scale_off, s * d.w + jg, s_e[tid]);
+          // the exponent is the same for every m tile of the slot: the first writes it
+          if (t == 0) stg_scale_e(ws + d.c_scale_off, s * d.w + jg, s_e[tid]);
           if (s_mx[tid] > 0u) max_scale_mx(ws + d.c_scale_off, s * d.w + jg, s_mx[tid]);
         }
       }
@@ -364,7 +399,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
       if (lane == 0) {
-        stg_scale_e(ws + d.c_scale_off, inst, e_out);
+        // the exponent is the same for every tile of the instance: its first tile writes it
+        if (t == 0 && wave == 0) stg_scale_e(ws + d.c_scale_off, inst, e_out);
         if (mx > 0.f) max_scale_mx(ws + d.c_scale_off, inst, __float_as_uint(mx));
       }
     }

@@ -117,13 +117,15 @@ __device__ __forceinline__ float segment_max(float v, int seg) {
   return v;
 }
 
-// record the output maximum: one atomic per wave, no block barrier
+// record the output maximum: at most one atomic per wave, no block barrier;
+// the exponent (the same for every block of the instance) is written by the
+// first wave of the block that covers the instance's first elements
 template <int FL>
 __device__ __forceinline__ void block_record(const NodeDesc& d, uint64_t ws, int64_t inst, const OutScale& s, float mx,
-                                             float* /*red*/) {
+                                             float* /*red*/, bool first_block) {
   if constexpr ((FL & kMixBit) != 0) {
     mx = wave_max(mx);
-    if ((threadIdx.x & 63) == 0) record_scale<FL>(d, ws, inst, s, mx, true);
+    if ((threadIdx.x & 63) == 0) record_scale<FL>(d, ws, inst, s, mx, first_block && threadIdx.x == 0);
   }
 }
 
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(256) void k_wide(NodeDesc d, uint64_t ws, const int
         mx = fmaxf(mx, put<FL>(ip.pc, oc[r] + cn, c, s));
       }
     }
-    block_record<FL>(d, ws, ip.inst, s, mx, red);
+    block_record<FL>(d, ws, ip.inst, s, mx, red, hi0 == 0);
     __syncthreads();  // Bs is rewritten next iteration
   }
 }
@@ -250,7 +252,7 @@ __global__ __launch_bounds__(256) void k_narrow(NodeDesc d, uint64_t ws, const i
       // lanes of one instance are contiguous; reduce within segments of a wave
       mx = segment_max(mx, seg);
       const int lane = threadIdx.x & 63;
-      if (live && (lane & (seg - 1)) == 0) record_scale<FL>(d, ws, inst, s, mx, true);
+      if (live && (lane & (seg - 1)) == 0) record_scale<FL>(d, ws, inst, s, mx, ((uint32_t)g & mmask) == 0);
     }
   }
 }
@@ -340,7 +342,7 @@ __global__ __launch_bounds__(256) void k_kred(NodeDesc d, uint64_t ws, const int
 #pragma unroll
       for (int n = 0; n < NB; ++n) mx = fmaxf(mx, put<FL>(ip.pc, oc + tcn[n], acc[n], s));
     }
-    block_record<FL>(d, ws, ip.inst, s, mx, red);
+    block_record<FL>(d, ws, ip.inst, s, mx, red, chunk == 0);
     if (KS > 1) __syncthreads();  // part[] is rewritten next iteration
   }
 }
@@ -381,7 +383,8 @@ __global__ __launch_bounds__(256) void k_generic(NodeDesc d, uint64_t ws, const 
     if constexpr ((FL & kMixBit) != 0) {
       mx = segment_max(mx, seg);
       const int lane = threadIdx.x & 63;
-      if (live && (lane & (seg - 1)) == 0) record_scale<FL>(d, ws, inst, s, mx, true);
+      if (live && (lane & (seg - 1)) == 0)
+        record_scale<FL>(d, ws, inst, s, mx, ((uint64_t)g & (((uint64_t)1 << cb) - 1)) == 0);
     }
   }
 }
@@ -466,6 +469,9 @@ hipError_t launch_stream_h(const NodeDesc& d, uint64_t ws, const int64_t* sig, h
   const int fl = (d.A.half ? 1 : 0) | (d.B.half ? 2 : 0) | (d.c_half ? 4 : 0);
   switch (fl) {
     case 0: return launch_stream_fl<kMixBit | 0>(d, ws, sig, st);
+    case 1: return launch_stream_fl<kMixBit | 1>(d, ws, sig, st);
+    case 2: return launch_stream_fl<kMixBit | 2>(d, ws, sig, st);
+    case 3: return launch_stream_fl<kMixBit | 3>(d, ws, sig, st);
     case 4: return launch_stream_fl<kMixBit | 4>(d, ws, sig, st);
     case 5: return launch_stream_fl<kMixBit | 5>(d, ws, sig, st);
     case 6: return launch_stream_fl<kMixBit | 6>(d, ws, sig, st);

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cstdio>
 #include <cstdlib>
@@ -87,6 +88,12 @@ int guarded(F&& f) {
 }
 
 constexpr uint64_t kAlign = 256;
+
+// complex-half plans: intermediates outside the twig stored in FP16 unless
+// the caller sets matnc_plan_options_t.half_extra -- kDefaultHalfExtra for
+// batches of at least kHalfExtraMinAmps amplitudes, none for smaller ones
+constexpr int kDefaultHalfExtra = 8;
+constexpr int64_t kHalfExtraMinAmps = 4096;
 
 // bytes per stored element of node v: complex64 (8) unless the plan is
 // complex-half and v is an FP16-stored branch tensor (4)
@@ -246,15 +253,53 @@ void build_steps(Plan& P) {
   P.cmac_single = P.cmac_multi = P.cmac_inv = P.cmac_total = 0;
   P.bytes_slice = P.bytes_inv = 0;
   const double nsl = std::ldexp(1.0, (int)P.sliced.size());
-  // complex-half storage policy: FP16 with per-instance exponents for the
-  // tensors of the twig, whose reuse width is at least a quarter of the
-  // distinct bitstrings -- that is where the bytes move, and each instance
-  // feeds only a few amplitudes, so rounding errors stay independent across
-  // amplitudes instead of shifting the whole batch (and its XEB) together.
-  // Leaves, the stem and the narrow part of the branch stay FP32.
+  // complex-half storage policy: FP16 with per-instance exponents for
+  //  * the tensors of the twig, whose reuse width is at least a quarter of
+  //    the distinct bitstrings -- each instance feeds only a few amplitudes,
+  //    so their rounding errors stay independent across amplitudes;
+  //  * the P.half_extra other intermediates (stem and narrow branch) whose
+  //    steps carry the most estimated FP32 time: they then run on the FP16
+  //    MFMA kernels and move half the bytes.  Each adds one FP16 rounding
+  //    (relative rms about 2^-11 / sqrt(3)) shared by every amplitude, so
+  //    their number is the precision budget of the plan.
+  // Leaves and the other intermediates stay FP32.
+  std::vector<double> t32(P.n_nodes, 0.0);
+  for (int v = nt; v < P.n_nodes; ++v) {
+    const PNode& V = P.nodes[v];
+    const PNode& ca = P.nodes[V.a];
+    const PNode& cb = P.nodes[V.b];
+    std::vector<int> fa(ca.idx), fb(cb.idx);
+    std::sort(fa.begin(), fa.end());
+    std::sort(fb.begin(), fb.end());
+    std::vector<int> sh;
+    std::set_intersection(fa.begin(), fa.end(), fb.begin(), fb.end(), std::back_inserter(sh));
+    const int kb = (int)sh.size();
+    const int ra = (int)std::max(fa.size(), fb.size()), rb = (int)std::min(fa.size(), fb.size());
+    const int mb = ra - kb, nb = rb - kb;
+    const double w = (double)V.keys.size();
+    const double wa = (double)(fa.size() >= fb.size() ? ca : cb).keys.size();
+    const double wb = (double)(fa.size() >= fb.size() ? cb : ca).keys.size();
+    const double flops = 8.0 * w * std::ldexp(1.0, mb + nb + kb);
+    const double bytes = 8.0 * (w * std::ldexp(1.0, (int)V.idx.size()) + wa * std::ldexp(1.0, ra) +
+                                wb * std::ldexp(1.0, rb));
+    const bool gemm = nb + kb >= 8 && mb >= 6 && nb >= 5 && kb >= 3;
+    t32[v] = std::max(flops / (gemm ? 100e12 : 40e12), bytes / 3e12) * (V.dep ? nsl : 1.0);
+  }
+  std::vector<char> extra(P.n_nodes, 0);
+  if (P.precision == MATNC_CHALF && P.half_extra > 0) {
+    std::vector<int> order;
+    for (int v = nt; v < P.n_nodes; ++v) {
+      const int64_t w = (int64_t)P.nodes[v].keys.size();
+      if (!(w > 1 && 4 * w >= P.n_unique)) order.push_back(v);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return t32[x] > t32[y]; });
+    for (size_t i = 0; i < order.size() && (int)i < P.half_extra; ++i) extra[order[i]] = 1;
+  }
+  P.n_half = 0;
   for (int v = 0; v < P.n_nodes; ++v) {
     const int64_t w = (int64_t)P.nodes[v].keys.size();
-    P.nodes[v].half_store = P.precision == MATNC_CHALF && v >= nt && w > 1 && 4 * w >= P.n_unique;
+    P.nodes[v].half_store = P.precision == MATNC_CHALF && v >= nt && ((w > 1 && 4 * w >= P.n_unique) || extra[v]);
+    P.n_half += P.nodes[v].half_store ? 1 : 0;
   }
   for (int v = nt; v < P.n_nodes; ++v) {
     PNode& V = P.nodes[v];
@@ -713,7 +758,7 @@ OpDesc operand_desc(const Plan& P, int child, uint64_t gmap_off, int c) {
   const PNode& C = P.nodes[child];
   OpDesc o;
   std::memset(&o, 0, sizeof(o));
-  o.off = C.off;
+  o.off = C.off + (child >= P.net.n_tensors ? P.arena_delta : 0);
   o.inst_bytes = C.inst_elems * eb_of(P, child);
   o.half = C.half_store ? 1 : 0;
   o.gmap_off = gmap_off;
@@ -739,7 +784,7 @@ NodeDesc node_desc(const Plan& P, int v, int nb, int c = 0) {
   const uint64_t gb = pos >= 0 ? P.chunks[c].nodes[pos].gb_off : V.gb_off;
   d.A = operand_desc(P, ca, ga, c);
   d.B = operand_desc(P, cb, gb, c);
-  d.c_off = V.off;
+  d.c_off = V.off + P.arena_delta;
   d.c_inst_bytes = V.inst_elems * eb_of(P, v);
   d.c_half = V.half_store ? 1 : 0;
   d.tab_off = V.tab_off;
@@ -765,11 +810,20 @@ OpDesc root_desc(const Plan& P, int c) {
   return operand_desc(P, root, P.chunks[c].rootloc_off, c);
 }
 
+// Queue plans that share an arena: before launching into it, a plan takes
+// it over; if another plan held it, this plan's stem cache is gone.
+void claim_arena(Plan& P) {
+  if (!P.share) return;
+  if (P.share->owner != P.share_id) P.inv_valid = false;
+  P.share->owner = P.share_id;
+}
+
 void launch_node(const Plan& P, const PNode& V, const NodeDesc& d, hipStream_t st) {
   const int64_t* sig = reinterpret_cast<const int64_t*>(P.ws + P.sigma_off);
   hipError_t e;
   if (V.kernel == 1 && !V.half_store) {
-    // FP32 MFMA; an FP16 consumer's scaling needs the output maxima: fan-out
+    // FP32 MFMA (an FP16-stored operand is widened exactly as it is loaded);
+    // an FP16 consumer's scaling needs the output maxima: fan-out
     // tiles record them in their epilogue, other tiles leave them to a
     // separate reduction pass (recording in the epilogue of the big tiles
     // raises their register use and cuts the occupancy)
@@ -784,8 +838,10 @@ void launch_node(const Plan& P, const PNode& V, const NodeDesc& d, hipStream_t s
   } else if (P.precision == MATNC_C64) {
     e = launch_stream(d, P.ws, sig, st);
   } else {
-    // FP32 tensors whose maximum nobody reads take the complex64 kernels
-    e = (V.half_store || V.rec_max) ? launch_stream_h(d, P.ws, sig, st) : launch_stream(d, P.ws, sig, st);
+    // steps with no FP16 operand or output and whose maximum nobody reads
+    // take the complex64 kernels
+    e = (V.half_store || V.rec_max || d.A.half || d.B.half) ? launch_stream_h(d, P.ws, sig, st)
+                                                             : launch_stream(d, P.ws, sig, st);
   }
   hip_check(e, "kernel launch");
 }
@@ -918,6 +974,181 @@ void write_tune_cache(const char* path, const std::map<std::string, int>& m) {
   if (std::rename(tmp.c_str(), path) != 0) fail(MATNC_E_INVALID, std::string("cannot write tuning cache ") + path);
 }
 
+// ---------------------------------------------------------------------------
+// single pairwise contractions (matnc_contract)
+
+// scratch of one call: a zero head (int64 sigma slot at byte 0, a zero
+// int32 gather entry at byte 8), then the six offset tables
+constexpr size_t kContractScratchBytes = kAlign + (size_t)TAB_COUNT * kTabSize * 4;
+
+struct TabPos {
+  int8_t pos[TAB_COUNT][32];  // storage bit of coordinate bit i, per table class
+  int32_t nbits[TAB_COUNT];
+};
+
+struct ContractCall {
+  int64_t batch;
+  int nm, nn, nk;
+  int kind, cfg;  // 0 streaming, 1 MFMA configuration cfg
+  TabPos pos;
+};
+
+// validates the arguments of one contraction and picks its kernel
+ContractCall contract_call(int64_t batch, int nm, int nn, int nk, const int* posA_m, const int* posA_k,
+                           const int* posB_k, const int* posB_n, const int* posC_m, const int* posC_n, int kernel) {
+  if (batch < 0) fail(MATNC_E_INVALID, "batch must be >= 0");
+  if (nm < 0 || nn < 0 || nk < 0 || nm + nk > 32 || nn + nk > 32 || nm + nn > 32)
+    fail(MATNC_E_INVALID, "ranks must be <= 32");
+  if ((nm && (!posA_m || !posC_m)) || (nn && (!posB_n || !posC_n)) || (nk && (!posA_k || !posB_k)))
+    fail(MATNC_E_INVALID, "null position array");
+  auto check_perm = [](std::vector<int> p, const char* what) {
+    std::sort(p.begin(), p.end());
+    for (size_t i = 0; i < p.size(); ++i)
+      if (p[i] != (int)i) fail(MATNC_E_INVALID, std::string(what) + " positions are not a permutation");
+  };
+  std::vector<int> pa, pb, pc;
+  for (int t = 0; t < nm; ++t) pa.push_back(posA_m[t]);
+  for (int t = 0; t < nk; ++t) pa.push_back(posA_k[t]);
+  for (int t = 0; t < nk; ++t) pb.push_back(posB_k[t]);
+  for (int t = 0; t < nn; ++t) pb.push_back(posB_n[t]);
+  for (int t = 0; t < nm; ++t) pc.push_back(posC_m[t]);
+  for (int t = 0; t < nn; ++t) pc.push_back(posC_n[t]);
+  check_perm(pa, "A");
+  check_perm(pb, "B");
+  check_perm(pc, "C");
+  ContractCall c;
+  std::memset(&c, 0, sizeof(c));
+  c.batch = batch;
+  c.nm = nm;
+  c.nn = nn;
+  c.nk = nk;
+  c.kind = 0;
+  c.cfg = -1;
+  if (kernel == -1) {
+    if (nn + nk > 8) {
+      const int order[] = {1, 0, 3, 2};
+      for (int k : order)
+        if (mfma_config_fits(k, nm, nn, nk)) {
+          c.kind = 1;
+          c.cfg = k;
+          break;
+        }
+    }
+  } else if (kernel == 0) {
+    c.kind = 0;
+  } else if (kernel == 1) {
+    for (int k = 0; k < mfma_config_count() && c.cfg < 0; ++k)
+      if (mfma_config_fits(k, nm, nn, nk)) c.cfg = k;
+    if (c.cfg < 0) fail(MATNC_E_INVALID, "no MFMA tile fits this shape");
+    c.kind = 1;
+  } else if (kernel >= 100 && kernel < 100 + mfma_config_count()) {
+    c.cfg = kernel - 100;
+    if (!mfma_config_fits(c.cfg, nm, nn, nk)) fail(MATNC_E_INVALID, "MFMA tile does not fit this shape");
+    c.kind = 1;
+  } else {
+    fail(MATNC_E_INVALID, "unknown kernel selector");
+  }
+  const int* src[TAB_COUNT];
+  src[TAB_AM] = posA_m;
+  src[TAB_CM] = posC_m;
+  src[TAB_BN] = posB_n;
+  src[TAB_CN] = posC_n;
+  src[TAB_AK] = posA_k;
+  src[TAB_BK] = posB_k;
+  const int nb[TAB_COUNT] = {nm, nm, nn, nn, nk, nk};
+  for (int t = 0; t < TAB_COUNT; ++t) {
+    c.pos.nbits[t] = nb[t];
+    for (int i = 0; i < nb[t]; ++i) c.pos.pos[t][i] = (int8_t)src[t][i];
+  }
+  return c;
+}
+
+// the contraction of one call; base = device address of its scratch
+void launch_contract(const ContractCall& c, const void* A, const void* B, void* C, uint64_t base, hipStream_t st) {
+  NodeDesc d;
+  std::memset(&d, 0, sizeof(d));
+  auto op = [&](const void* p, int rank) {
+    OpDesc o;
+    std::memset(&o, 0, sizeof(o));
+    o.off = reinterpret_cast<uint64_t>(p);
+    o.inst_bytes = 8ull << rank;
+    o.gmap_off = base + 8;  // a single zero entry
+    o.w_child = 1;
+    o.dep = 1;
+    o.nsv = 1;
+    return o;
+  };
+  d.A = op(A, c.nm + c.nk);
+  d.B = op(B, c.nn + c.nk);
+  d.c_off = reinterpret_cast<uint64_t>(C);
+  d.c_inst_bytes = 8ull << (c.nm + c.nn);
+  d.tab_off = base + kAlign;
+  d.w = 1;
+  d.dep = 1;
+  d.n_inst = c.batch;
+  d.mbits = c.nm;
+  d.nbits = c.nn;
+  d.kbits = c.nk;
+  const int64_t* sig = reinterpret_cast<const int64_t*>(base);
+  hipError_t e = c.kind == 1 ? launch_mfma(d, c.cfg, 0, sig, st) : launch_stream(d, 0, sig, st);
+  hip_check(e, "contract launch");
+}
+
+// attaches plan P to its static region at dev_workspace (and its arena at
+// dev_workspace + static_bytes + arena_delta), uploads the static region
+void bind_plan(Plan& P, void* dev_workspace, size_t bytes, void* hip_stream, uint64_t arena_delta,
+               std::shared_ptr<ArenaShare> share) {
+  release_graph(P);
+  P.bound = false;
+  P.ws = reinterpret_cast<uint64_t>(dev_workspace);
+  P.ws_bytes = bytes;
+  P.arena_delta = arena_delta;
+  P.share = std::move(share);
+  if (P.share) {
+    static std::atomic<uint64_t> next_id{0};
+    P.share_id = ++next_id;
+  }
+  P.stream = reinterpret_cast<hipStream_t>(hip_stream);
+  // host image of the static region
+  P.staging.assign(P.static_bytes, 0);
+  const int nt = P.net.n_tensors;
+  for (int v = nt; v < P.n_nodes; ++v) {
+    const PNode& V = P.nodes[v];
+    uint32_t* T = reinterpret_cast<uint32_t*>(P.staging.data() + V.tab_off);
+    const PNode& A = P.nodes[V.swap ? V.b : V.a];
+    const PNode& B = P.nodes[V.swap ? V.a : V.b];
+    fill_table(T + TAB_AM * kTabSize, V.M, A.idx);
+    fill_table(T + TAB_CM * kTabSize, V.M, V.idx);
+    fill_table(T + TAB_BN * kTabSize, V.N, B.idx);
+    fill_table(T + TAB_CN * kTabSize, V.N, V.idx);
+    fill_table(T + TAB_AK * kTabSize, V.K, A.idx);
+    fill_table(T + TAB_BK * kTabSize, V.K, B.idx);
+    if (P.chunk_pos[v] < 0) {
+      std::memcpy(P.staging.data() + V.ga_off, V.ga.data(), V.ga.size() * 4);
+      std::memcpy(P.staging.data() + V.gb_off, V.gb.data(), V.gb.size() * 4);
+      for (int t = 0; t < 2; ++t)
+        std::memcpy(P.staging.data() + V.fan_off[t], V.fanv[t].data(), V.fanv[t].size() * 4);
+    }
+  }
+  for (const Chunk& C : P.chunks) {
+    for (const ChunkNode& N : C.nodes) {
+      std::memcpy(P.staging.data() + N.ga_off, N.ga.data(), N.ga.size() * 4);
+      std::memcpy(P.staging.data() + N.gb_off, N.gb.data(), N.gb.size() * 4);
+      for (int t = 0; t < 2; ++t)
+        std::memcpy(P.staging.data() + N.fan_off[t], N.fanv[t].data(), N.fanv[t].size() * 4);
+    }
+    std::memcpy(P.staging.data() + C.rows_off, C.rows.data(), C.rows.size() * 4);
+    std::memcpy(P.staging.data() + C.rootloc_off, C.rootloc.data(), C.rootloc.size() * 4);
+  }
+  for (int l = 0; l < nt; ++l) fill_leaf_data(P, l, P.staging.data());
+  hip_check(hipMemcpyAsync(dev_workspace, P.staging.data(), P.static_bytes, hipMemcpyHostToDevice, P.stream),
+            "upload static region");
+  hip_check(hipStreamSynchronize(P.stream), "upload static region");
+  P.bound = true;
+  P.inv_valid = false;
+  ++P.generation;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -986,7 +1217,23 @@ int matnc_network_destroy(matnc_network net) {
 int matnc_plan_create(matnc_network net, const int* pairs, int n_sliced, const int* sliced_ids, int n_open,
                       const int* open_qubits, int64_t k, const uint64_t* bitstrings, int precision, int max_rank,
                       int slice_batch, size_t memory_budget, matnc_plan* out) {
+  matnc_plan_options_t o;
+  std::memset(&o, 0, sizeof(o));
+  o.slice_batch = slice_batch;
+  o.memory_budget = memory_budget;
+  o.half_extra = -1;
+  return matnc_plan_create_ex(net, pairs, n_sliced, sliced_ids, n_open, open_qubits, k, bitstrings, precision,
+                              max_rank, &o, out);
+}
+
+int matnc_plan_create_ex(matnc_network net, const int* pairs, int n_sliced, const int* sliced_ids, int n_open,
+                         const int* open_qubits, int64_t k, const uint64_t* bitstrings, int precision, int max_rank,
+                         const matnc_plan_options_t* opts, matnc_plan* out) {
   return guarded([&] {
+    if (!opts) fail(MATNC_E_INVALID, "null options");
+    const int slice_batch = opts->slice_batch;
+    const size_t memory_budget = opts->memory_budget;
+    if (opts->half_extra < -1) fail(MATNC_E_INVALID, "half_extra must be >= -1");
     if (!net || !out) fail(MATNC_E_INVALID, "null argument");
     const Network& N = net->net;
     const int nt = N.n_tensors;
@@ -1009,6 +1256,11 @@ int matnc_plan_create(matnc_network net, const int* pairs, int n_sliced, const i
     P.max_rank_cap = max_rank;
     P.batch = slice_batch;
     P.memory_budget = memory_budget;
+    // the XEB of K amplitudes with relative errors of rms e moves by about
+    // c e / sqrt(K) (c of a few units measured), so smaller batches keep the
+    // stem in FP32
+    const int64_t n_amps = k << n_open;
+    P.half_extra = opts->half_extra >= 0 ? opts->half_extra : (n_amps >= kHalfExtraMinAmps ? kDefaultHalfExtra : 0);
     // tree
     std::vector<char> used(2 * nt - 1, 0);
     for (int j = 0; j < nt - 1; ++j) {
@@ -1077,6 +1329,7 @@ int matnc_plan_info(matnc_plan plan, matnc_plan_info_t* info) {
     I.n_chunks = P.n_chunks;
     I.n_fan_nodes = 0;
     for (int v = P.net.n_tensors; v < P.n_nodes; ++v) I.n_fan_nodes += P.nodes[v].fan ? 1 : 0;
+    I.n_half_nodes = P.n_half;
     *info = I;
   });
 }
@@ -1114,49 +1367,7 @@ int matnc_plan_bind(matnc_plan plan, void* dev_workspace, size_t bytes, void* hi
     if (bytes < P.workspace_bytes)
       fail(MATNC_E_NOMEM, "workspace has " + std::to_string(bytes) + " bytes, plan needs " +
                               std::to_string(P.workspace_bytes));
-    release_graph(P);
-    P.bound = false;
-    P.ws = reinterpret_cast<uint64_t>(dev_workspace);
-    P.ws_bytes = bytes;
-    P.stream = reinterpret_cast<hipStream_t>(hip_stream);
-    // host image of the static region
-    P.staging.assign(P.static_bytes, 0);
-    const int nt = P.net.n_tensors;
-    for (int v = nt; v < P.n_nodes; ++v) {
-      const PNode& V = P.nodes[v];
-      uint32_t* T = reinterpret_cast<uint32_t*>(P.staging.data() + V.tab_off);
-      const PNode& A = P.nodes[V.swap ? V.b : V.a];
-      const PNode& B = P.nodes[V.swap ? V.a : V.b];
-      fill_table(T + TAB_AM * kTabSize, V.M, A.idx);
-      fill_table(T + TAB_CM * kTabSize, V.M, V.idx);
-      fill_table(T + TAB_BN * kTabSize, V.N, B.idx);
-      fill_table(T + TAB_CN * kTabSize, V.N, V.idx);
-      fill_table(T + TAB_AK * kTabSize, V.K, A.idx);
-      fill_table(T + TAB_BK * kTabSize, V.K, B.idx);
-      if (P.chunk_pos[v] < 0) {
-        std::memcpy(P.staging.data() + V.ga_off, V.ga.data(), V.ga.size() * 4);
-        std::memcpy(P.staging.data() + V.gb_off, V.gb.data(), V.gb.size() * 4);
-        for (int t = 0; t < 2; ++t)
-          std::memcpy(P.staging.data() + V.fan_off[t], V.fanv[t].data(), V.fanv[t].size() * 4);
-      }
-    }
-    for (const Chunk& C : P.chunks) {
-      for (const ChunkNode& N : C.nodes) {
-        std::memcpy(P.staging.data() + N.ga_off, N.ga.data(), N.ga.size() * 4);
-        std::memcpy(P.staging.data() + N.gb_off, N.gb.data(), N.gb.size() * 4);
-        for (int t = 0; t < 2; ++t)
-          std::memcpy(P.staging.data() + N.fan_off[t], N.fanv[t].data(), N.fanv[t].size() * 4);
-      }
-      std::memcpy(P.staging.data() + C.rows_off, C.rows.data(), C.rows.size() * 4);
-      std::memcpy(P.staging.data() + C.rootloc_off, C.rootloc.data(), C.rootloc.size() * 4);
-    }
-    for (int l = 0; l < nt; ++l) fill_leaf_data(P, l, P.staging.data());
-    hip_check(hipMemcpyAsync(dev_workspace, P.staging.data(), P.static_bytes, hipMemcpyHostToDevice, P.stream),
-              "upload static region");
-    hip_check(hipStreamSynchronize(P.stream), "upload static region");
-    P.bound = true;
-    P.inv_valid = false;
-    ++P.generation;
+    bind_plan(P, dev_workspace, bytes, hip_stream, 0, nullptr);
   });
 }
 
@@ -1170,6 +1381,7 @@ int matnc_execute(matnc_plan plan, int64_t slice_begin, int64_t slice_end, doubl
     if (slice_begin < 0 || slice_end < slice_begin || slice_end > ns) fail(MATNC_E_INVALID, "bad slice range");
     hipStream_t st = P.stream;
     int64_t* sig = reinterpret_cast<int64_t*>(P.ws + P.sigma_off);
+    claim_arena(P);
     if (!P.inv_valid) {
       hip_check(launch_set_i64(sig, 0, st), "set sigma");
       launch_prologue(P, st);
@@ -1220,6 +1432,7 @@ int matnc_plan_autotune(matnc_plan plan, int reps, const char* cache_path) {
     if (!P.bound) fail(MATNC_E_STATE, "autotune before bind");
     if (reps < 1) fail(MATNC_E_INVALID, "reps must be >= 1");
     std::map<std::string, int> cache = read_tune_cache(cache_path);
+    claim_arena(P);
     hipStream_t st = P.stream;
     int64_t* sig = reinterpret_cast<int64_t*>(P.ws + P.sigma_off);
     hip_check(launch_set_i64(sig, 0, st), "set sigma");
@@ -1329,6 +1542,7 @@ int matnc_plan_profile(matnc_plan plan, int64_t slice_begin, int nb, float* time
       }
     } eg{ev};
     for (auto& e : ev) hip_check(hipEventCreate(&e), "event create");
+    claim_arena(P);
     hipStream_t st = P.stream;
     int64_t* sig = reinterpret_cast<int64_t*>(P.ws + P.sigma_off);
     hip_check(launch_set_i64(sig, 0, st), "set sigma");
@@ -1432,7 +1646,64 @@ int matnc_queue_execute(matnc_queue q, double* const* amps_dev, double* xeb_dev)
       q->key = key;
     }
     hip_check(hipGraphLaunch(q->exec, st), "queue graph launch");
-    for (auto p : q->plans) p->p.inv_valid = true;
+    // every plan's pass recomputed its stem cache; in a shared arena only
+    // the last plan's survives
+    for (auto p : q->plans) {
+      Plan& P = p->p;
+      if (P.share) {
+        P.inv_valid = false;
+      } else {
+        P.inv_valid = true;
+      }
+    }
+    if (q->plans.back()->p.share) {
+      Plan& L = q->plans.back()->p;
+      L.share->owner = L.share_id;
+      L.inv_valid = true;
+    }
+  });
+}
+
+int matnc_queue_workspace_bytes(matnc_queue q, size_t* out) {
+  return guarded([&] {
+    if (!q || !out) fail(MATNC_E_INVALID, "null argument");
+    uint64_t st = 0, arena = 0;
+    for (auto p : q->plans) {
+      const Plan& P = p->p;
+      st += align_up(P.static_bytes);
+      arena = std::max<uint64_t>(arena, P.workspace_bytes - P.static_bytes);
+    }
+    *out = (size_t)align_up(st + arena);
+  });
+}
+
+int matnc_queue_bind(matnc_queue q, void* dev_workspace, size_t bytes, void* hip_stream) {
+  return guarded([&] {
+    if (!q || !dev_workspace) fail(MATNC_E_INVALID, "null argument");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) fail(MATNC_E_INVALID, "workspace not 256-byte aligned");
+    size_t need = 0;
+    if (matnc_queue_workspace_bytes(q, &need) != MATNC_OK) fail(MATNC_E_INVALID, g_err);
+    if (bytes < need)
+      fail(MATNC_E_NOMEM, "workspace has " + std::to_string(bytes) + " bytes, queue needs " + std::to_string(need));
+    for (size_t i = 0; i < q->plans.size(); ++i)
+      for (size_t j = 0; j < i; ++j)
+        if (q->plans[i] == q->plans[j]) fail(MATNC_E_INVALID, "a plan occurs twice in the queue");
+    // static regions side by side, then one arena shared by all plans
+    uint64_t total_static = 0;
+    for (auto p : q->plans) total_static += align_up(p->p.static_bytes);
+    auto share = std::make_shared<ArenaShare>();
+    uint64_t prefix = 0;
+    for (auto p : q->plans) {
+      Plan& P = p->p;
+      const uint64_t delta = total_static - prefix - P.static_bytes;
+      bind_plan(P, static_cast<unsigned char*>(dev_workspace) + prefix, bytes - prefix, hip_stream, delta, share);
+      prefix += align_up(P.static_bytes);
+    }
+    if (q->exec) (void)hipGraphExecDestroy(q->exec);
+    if (q->graph) (void)hipGraphDestroy(q->graph);
+    q->exec = nullptr;
+    q->graph = nullptr;
+    q->key.clear();
   });
 }
 
@@ -1445,7 +1716,7 @@ int matnc_queue_destroy(matnc_queue q) {
   return MATNC_OK;
 }
 
-size_t matnc_contract_scratch_bytes(void) { return kAlign + (size_t)TAB_COUNT * kTabSize * 4; }
+size_t matnc_contract_scratch_bytes(void) { return kContractScratchBytes; }
 
 int matnc_mfma_config_count(void) { return mfma_config_count(); }
 
@@ -1454,103 +1725,27 @@ int matnc_contract(const void* A, const void* B, void* C, int64_t batch, int nm,
                    int kernel, void* dev_scratch, size_t scratch_bytes, void* hip_stream) {
   return guarded([&] {
     if (!A || !B || !C || !dev_scratch) fail(MATNC_E_INVALID, "null argument");
-    if (batch < 0) fail(MATNC_E_INVALID, "batch must be >= 0");
-    if (nm < 0 || nn < 0 || nk < 0 || nm + nk > 32 || nn + nk > 32 || nm + nn > 32)
-      fail(MATNC_E_INVALID, "ranks must be <= 32");
-    if ((nm && (!posA_m || !posC_m)) || (nn && (!posB_n || !posC_n)) || (nk && (!posA_k || !posB_k)))
-      fail(MATNC_E_INVALID, "null position array");
     if (reinterpret_cast<uintptr_t>(dev_scratch) % kAlign) fail(MATNC_E_INVALID, "scratch not 256-byte aligned");
     if (scratch_bytes < matnc_contract_scratch_bytes()) fail(MATNC_E_NOMEM, "scratch too small");
-    auto check_perm = [](std::vector<int> p, const char* what) {
-      std::sort(p.begin(), p.end());
-      for (size_t i = 0; i < p.size(); ++i)
-        if (p[i] != (int)i) fail(MATNC_E_INVALID, std::string(what) + " positions are not a permutation");
-    };
-    std::vector<int> pa, pb, pc;
-    for (int t = 0; t < nm; ++t) pa.push_back(posA_m[t]);
-    for (int t = 0; t < nk; ++t) pa.push_back(posA_k[t]);
-    for (int t = 0; t < nk; ++t) pb.push_back(posB_k[t]);
-    for (int t = 0; t < nn; ++t) pb.push_back(posB_n[t]);
-    for (int t = 0; t < nm; ++t) pc.push_back(posC_m[t]);
-    for (int t = 0; t < nn; ++t) pc.push_back(posC_n[t]);
-    check_perm(pa, "A");
-    check_perm(pb, "B");
-    check_perm(pc, "C");
-    int kind = 0, cfg = -1;
-    if (kernel == -1) {
-      if (nn + nk > 8) {
-        const int order[] = {1, 0, 3, 2};
-        for (int c : order)
-          if (mfma_config_fits(c, nm, nn, nk)) {
-            kind = 1;
-            cfg = c;
-            break;
-          }
-      }
-    } else if (kernel == 0) {
-      kind = 0;
-    } else if (kernel == 1) {
-      for (int c = 0; c < mfma_config_count() && cfg < 0; ++c)
-        if (mfma_config_fits(c, nm, nn, nk)) cfg = c;
-      if (cfg < 0) fail(MATNC_E_INVALID, "no MFMA tile fits this shape");
-      kind = 1;
-    } else if (kernel >= 100 && kernel < 100 + mfma_config_count()) {
-      cfg = kernel - 100;
-      if (!mfma_config_fits(cfg, nm, nn, nk)) fail(MATNC_E_INVALID, "MFMA tile does not fit this shape");
-      kind = 1;
-    } else {
-      fail(MATNC_E_INVALID, "unknown kernel selector");
-    }
+    const ContractCall c = contract_call(batch, nm, nn, nk, posA_m, posA_k, posB_k, posB_n, posC_m, posC_n, kernel);
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    // host image of the scratch: zero head (sigma slot, one zero gather
+    // entry), then the six offset tables
     std::vector<unsigned char> img(matnc_contract_scratch_bytes(), 0);
     uint32_t* T = reinterpret_cast<uint32_t*>(img.data() + kAlign);
-    auto fill_pos = [](uint32_t* tab, const int* pos, int nbits) {
+    for (int t = 0; t < TAB_COUNT; ++t)
       for (int L = 0; L < kTabLevels; ++L)
         for (int e = 0; e < kTabEntries; ++e) {
           uint32_t off = 0;
-          for (int t = 0; t < 8; ++t) {
-            const int bit = 8 * L + t;
-            if (((e >> t) & 1) && bit < nbits) off += 1u << pos[bit];
+          for (int b = 0; b < 8; ++b) {
+            const int bit = 8 * L + b;
+            if (((e >> b) & 1) && bit < c.pos.nbits[t]) off += 1u << c.pos.pos[t][bit];
           }
-          tab[L * kTabEntries + e] = off;
+          T[t * kTabSize + L * kTabEntries + e] = off;
         }
-    };
-    fill_pos(T + TAB_AM * kTabSize, posA_m, nm);
-    fill_pos(T + TAB_CM * kTabSize, posC_m, nm);
-    fill_pos(T + TAB_BN * kTabSize, posB_n, nn);
-    fill_pos(T + TAB_CN * kTabSize, posC_n, nn);
-    fill_pos(T + TAB_AK * kTabSize, posA_k, nk);
-    fill_pos(T + TAB_BK * kTabSize, posB_k, nk);
-    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     hip_check(hipMemcpyAsync(dev_scratch, img.data(), img.size(), hipMemcpyHostToDevice, st), "upload tables");
     hip_check(hipStreamSynchronize(st), "upload tables");
-    const uint64_t base = reinterpret_cast<uint64_t>(dev_scratch);
-    NodeDesc d;
-    std::memset(&d, 0, sizeof(d));
-    auto op = [&](const void* p, int rank) {
-      OpDesc o;
-      std::memset(&o, 0, sizeof(o));
-      o.off = reinterpret_cast<uint64_t>(p);
-      o.inst_bytes = 8ull << rank;
-      o.gmap_off = base + 8;  // a single zero entry
-      o.w_child = 1;
-      o.dep = 1;
-      o.nsv = 1;
-      return o;
-    };
-    d.A = op(A, nm + nk);
-    d.B = op(B, nn + nk);
-    d.c_off = reinterpret_cast<uint64_t>(C);
-    d.c_inst_bytes = 8ull << (nm + nn);
-    d.tab_off = base + kAlign;
-    d.w = 1;
-    d.dep = 1;
-    d.n_inst = batch;
-    d.mbits = nm;
-    d.nbits = nn;
-    d.kbits = nk;
-    const int64_t* sig = reinterpret_cast<const int64_t*>(dev_scratch);
-    hipError_t e = kind == 1 ? launch_mfma(d, cfg, 0, sig, st) : launch_stream(d, 0, sig, st);
-    hip_check(e, "contract launch");
+    launch_contract(c, A, B, C, reinterpret_cast<uint64_t>(dev_scratch), st);
   });
 }
 

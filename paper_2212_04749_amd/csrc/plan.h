@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <complex>
+#include <memory>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -47,7 +48,7 @@ struct PNode {
   std::vector<int> sl_index;     // the sliced index ids, same order
   // step description (internal nodes)
   bool swap = false;             // true: operand A is child b
-  bool half_store = false;       // complex-half plans: stored as FP16 (twig tensors)
+  bool half_store = false;       // complex-half plans: stored as FP16 (twig, and the costliest other steps)
   bool rec_max = false;          // complex-half plans: FP32 tensor whose maximum an FP16 consumer needs
   int kernel = 0;                // 0 streaming, 1 MFMA
   int cfg = -1;
@@ -87,6 +88,14 @@ struct Chunk {
   uint64_t rows_off = 0, rootloc_off = 0;
 };
 
+// The plans of a queue bound to one workspace share one arena for their
+// intermediates (they run one after another); `owner` names the plan whose
+// tensors the arena holds now, so that the others know their stem cache is
+// gone.
+struct ArenaShare {
+  uint64_t owner = 0;
+};
+
 struct Plan {
   Network net;
   int n_nodes = 0;               // n_tensors + steps
@@ -99,6 +108,8 @@ struct Plan {
   int batch = 1;
   int elem_bytes = 8;
   uint64_t memory_budget = 0;    // 0 = no limit
+  int half_extra = 0;            // complex-half: FP16-stored intermediates outside the twig
+  int n_half = 0;                // complex-half: FP16-stored intermediates in all
   int n_chunks = 1;
   std::vector<Chunk> chunks;
   std::vector<int> chunk_pos;    // node id -> position in chunked (-1 if not there)
@@ -121,6 +132,9 @@ struct Plan {
   int n_mfma = 0;
   int64_t n_unique = 0;
   // binding
+  uint64_t arena_delta = 0;              // intermediates live at ws + off + arena_delta
+  std::shared_ptr<ArenaShare> share;     // set when the arena is shared with other plans
+  uint64_t share_id = 0;                 // this plan's name in share->owner
   bool bound = false;
   bool inv_valid = false;
   uint64_t ws = 0;

@@ -73,3 +73,44 @@ def test_native_statevector_matches_numpy():
     a = statevector.amplitudes(circ, words)
     b = sv_native.amplitudes(circ, words)
     assert np.max(np.abs(a - b)) < 1e-14
+
+
+def test_slice_refiner_reaches_a_local_optimum_of_the_multi_amplitude_loss():
+    # from the worst valid sliced set of the slicer's size, the refiner must
+    # end at a valid set whose loss is no higher, no lower than the
+    # brute-force best set, and that no single exchange improves
+    import itertools
+    from paper_2212_04749_amd import planner as P
+    from paper_2212_04749_amd.circuit_tn import build_network
+    from workload import GridSpec, random_circuit, uniform_bitstrings
+    net = build_network(random_circuit(GridSpec(3, 3), 8, 31))
+    words = uniform_bitstrings(9, 24, 32)
+    st = P.Structure.from_network(net)
+    pairs = P.greedy_pairs(st)
+    w = P.widths(P.build_tree(st, pairs), words)
+    cap = max(m.bit_count() for m in P.build_tree(st, pairs).masks) - 2
+    bonds = sorted(set(i for m in st.leaf_masks for i in P._bits(m)))
+    n_sl = len(P.slice_to_cap(st, pairs, w, cap, objective="flops")[0])
+
+    def loss(sl):
+        mask = sum(1 << i for i in sl)
+        t = P.build_tree(st, pairs, mask)
+        if max(m.bit_count() for m in t.masks) > cap:
+            return None
+        return P.costs(st, t, w, mask).total
+
+    valid = [(loss(c), c) for c in itertools.combinations(bonds, n_sl)]
+    valid = [(v, c) for v, c in valid if v is not None]
+    best = min(v for v, _ in valid)
+    start_loss, start = max(valid)
+    s2, c2 = P.refine_slices(st, pairs, w, list(start), cap, objective="flops", exact=True)
+    assert len(s2) == n_sl and loss(s2) == c2.total
+    assert best <= c2.total < start_loss
+    for pos in range(n_sl):
+        for j in bonds:
+            if j in s2:
+                continue
+            trial = list(s2)
+            trial[pos] = j
+            v = loss(trial)
+            assert v is None or v >= c2.total * (1 - 1e-9)
