@@ -1,8 +1,9 @@
 #!/usr/bin/env python3
 """Throughput of the sliced multi-amplitude contraction on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload C2]
-                    [--precision c64|chalf] [--slice-batch B] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload C3]
+                    [--precision chalf|c64] [--beside-steps K2] [--no-secondary]
+                    [--slice-batch B] [--no-cpu-baseline]
 
 One step is one complete pass of the hot path over the workload's batch:
 the slice-invariant (stem) nodes, every slice of the sliced network in
@@ -11,11 +12,21 @@ FP64 slice-sum into the amplitudes and the FP64 linear XEB.  Inputs (leaf
 tensors, reuse maps, offset tables) are resident in HBM before the timed
 region; planning and upload are reported separately.
 
+Default: the 6x6 depth-14 batching workload (2^14 amplitudes as 64 bitstring
+groups x 8 open legs, 256 slices, its stored plan), complex-half for the
+headline (W warm-up passes, K timed passes), complex64 on the same plan
+beside it (one warm-up, K2 timed passes), and the 5x6 depth-12 workload
+(4096 bitstrings) in both precisions as a secondary entry.  The first
+warm-up pass of the 6x6 legs runs the permutation circuit of the same grid
+(its leaves swapped in with matnc_plan_set_tensor; exact amplitudes known,
+stored in tests/golden/c3_permutation.json): its error is the error figure
+of the line, since the random circuit is beyond any FP64 reference.
+
 Prints one JSON line: amplitudes/s of the whole job (value), sustained
-complex TFLOP/s, the error of the amplitudes against the stored FP64
-oracle values, a roofline entry for the dominant kernel (HIP-event timings
-of a profiled pass on the plan's stream) and the oracle timed on the host
-cores on a bounded sample.
+complex TFLOP/s, the error of the amplitudes against stored FP64 oracle
+values, a roofline entry for the dominant kernel (HIP-event timings of a
+profiled pass on the plan's stream) and the oracle timed on the host cores
+on a bounded sample.
 """
 
 from __future__ import annotations
@@ -31,6 +42,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp32": 157.3, "fp16": 2516.6}  # dense MFMA
 PEAK_HBM_GBS = 8000.0
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+METRIC = "sustained complex TFLOP/s + amplitudes/sec per slice-batch at stated err vs FP64"
+PRECISION_NAME = {"c64": "complex64", "chalf": "complex-half"}
 
 
 def log(msg: str) -> None:
@@ -42,12 +56,14 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4", "C5"])
+    p.add_argument("--workload", default="C3", choices=["C1", "C2", "C3", "C4", "C5", "PT"],
+                   help="C1..C5 the workloads; PT the fidelity workload (Eq. (2), Fig. 4)")
     p.add_argument("--max-est-s", type=float, default=100.0,
                    help="uneven batch (C5): leave out circuits whose plan's estimated time exceeds this")
-    p.add_argument("--precision", default="c64", choices=["c64", "chalf"])
+    p.add_argument("--precision", default=None, choices=["c64", "chalf"],
+                   help="headline precision (default: complex-half, complex64 for the 4x4 and 5x6 workloads)")
     p.add_argument("--slice-batch", type=int, default=0, help="0 = workload default")
-    p.add_argument("--trials", type=int, default=32, help="order-search candidates")
+    p.add_argument("--trials", type=int, default=32, help="order-search candidates (--replan, 4x4)")
     p.add_argument("--partition-trials", type=int, default=-1,
                    help="bisection candidates of the order search (-1: 16 for the 36- and 53-qubit "
                         "workloads, none otherwise)")
@@ -55,13 +71,13 @@ def parse():
                    help="time N consecutive slices (seeded start) instead of all of them and project the "
                         "full-job rate (the large workloads); 0 = every slice")
     p.add_argument("--replan", action="store_true",
-                   help="6x6 and 53-qubit workloads: search a plan instead of loading the stored one")
+                   help="search a plan instead of loading the stored one (5x6, 6x6 and 53-qubit workloads)")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--beside", action="store_true",
-                   help="complex64 runs: also time complex-half on the same plan (default for the small workloads)")
-    p.add_argument("--no-beside", action="store_true")
+    p.add_argument("--beside-steps", type=int, default=2,
+                   help="timed passes of the other precision on the same plan (0: leave it out)")
+    p.add_argument("--no-secondary", action="store_true", help="6x6 default: leave out the 5x6 entry")
     p.add_argument("--no-autotune", action="store_true", help="keep the heuristic MFMA tile choice")
-    p.add_argument("--profile-out", default="", help="write the per-step profile as JSON")
+    p.add_argument("--profile-out", default="", help="write the per-step profile of the headline leg as JSON")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run a plain device-to-device copy of MIB MiB five times (calibrates the "
                         "HBM byte counters of a profiler against a known traffic) and exit")
@@ -113,14 +129,28 @@ def autotune(run) -> None:
         os.remove(path)
 
 
-def workload_description(name, w, info, spec):
+def stored_plan(name, net, words, open_qubits):
+    """The stored plan of a workload (plans/make_*.py: seconds to tens of
+    minutes of host search) with its cost reports."""
+    import importlib
+    from paper_2212_04749_amd import planner
+    e = importlib.import_module(f"paper_2212_04749_amd.plans.make_{name.lower()}").load()
+    plan = planner.plan_from(net, words, open_qubits, e["pairs"], e["sliced"], "stored:" + e["method"])
+    return plan, e
+
+
+def workload_description(name, w, info, spec, e):
     g = w.grid
     shape = f"{g.rows}x{g.cols}" + (f" minus {len(g.removed)} site" if g.removed else "")
+    greedy = (e or {}).get("greedy_report") or {}
+    plan_txt = f"; plan: {spec.method}"
+    if greedy.get("cmac_total"):
+        plan_txt += f" (the greedy order sliced to the same cap: {greedy['cmac_total']:.2e} CMAC)"
     return {
         "workload": f"{name}: {shape} grid RQC ({w.n_qubits} qubits), depth {w.depth}, "
                     f"fSim(pi/2,pi/6), {w.k} uniform bitstrings" +
                     (f" x 2^{len(w.open_qubits)} open legs" if w.open_qubits else "") +
-                    f", rank cap {spec.cap}, {info.n_slices} slices",
+                    f", rank cap {spec.cap}, {info.n_slices} slices" + plan_txt,
         "n_qubits": w.n_qubits,
         "depth": w.depth,
         "bitstrings": w.k,
@@ -132,32 +162,278 @@ def workload_description(name, w, info, spec):
         "cmac_total": float(info.cmac_total),
         "kS_over_Sk": float(info.n_unique * info.cmac_single / info.cmac_multi),
         "plan": spec.method,
+        "greedy_plan": greedy or None,
     }
 
 
-def reference_error(name, run, amps_np):
-    """Relative error vs the stored FP64 oracle amplitudes, where stored."""
+def _golden_amps(g):
     import numpy as np
-    path = {"C2": "c2_subset.json", "C1": None}.get(name)
-    if name == "C1":
-        from oracle import statevector
-        from workload import CONFIGS
-        w = CONFIGS["C1"]
-        ref = statevector.amplitudes(w.circuit(), w.bitstrings())
-        got = amps_np[:, 0]
-    elif path and os.path.exists(os.path.join(ROOT, "tests", "golden", path)):
-        g = json.load(open(os.path.join(ROOT, "tests", "golden", path)))
-        ref = np.array([complex(a, b) for a, b in g["amps"]])
-        got = amps_np[np.array(g["indices"]), 0]
-    else:
+    return np.array([complex(a, b) for a, b in g["amps"]])
+
+
+def errors(got, ref, n_qubits):
+    import numpy as np
+    got, ref = np.asarray(got).reshape(-1), np.asarray(ref).reshape(-1)
+    xeb_gpu = float(np.ldexp(np.mean(np.abs(got) ** 2), n_qubits) - 1)
+    xeb_ref = float(np.ldexp(np.mean(np.abs(ref) ** 2), n_qubits) - 1)
+    return {"rel_err": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            "max_abs_err_over_rms": float(np.max(np.abs(got - ref)) / np.sqrt(np.mean(np.abs(ref) ** 2))),
+            "samples": int(got.size), "xeb_abs_err_on_samples": abs(xeb_gpu - xeb_ref)}
+
+
+def reference_error(name, amps_c, n_qubits):
+    """Error against the stored FP64 oracle amplitudes of the workload's
+    random circuit (tests/golden, written by oracle-only scripts), where
+    stored: all 64 of the 4x4 batch, a 256-bitstring subset of the 5x6 one."""
+    import numpy as np
+    path = {"C1": "c1_all.json", "C2": "c2_subset.json"}.get(name)
+    if not path or not os.path.exists(os.path.join(GOLDEN, path)):
         return None
-    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    max_over_rms = float(np.max(np.abs(got - ref)) / np.sqrt(np.mean(np.abs(ref) ** 2)))
-    n = run.net.n_qubits
-    xeb_gpu = float(np.ldexp(np.mean(np.abs(got) ** 2), n) - 1)
-    xeb_ref = float(np.ldexp(np.mean(np.abs(ref) ** 2), n) - 1)
-    return {"rel_err": err, "max_abs_err_over_rms": max_over_rms, "samples": int(len(ref)),
-            "xeb_abs_err_on_samples": abs(xeb_gpu - xeb_ref)}
+    g = json.load(open(os.path.join(GOLDEN, path)))
+    ref = _golden_amps(g)
+    idx = np.array(g["indices"]) if "indices" in g else np.arange(len(ref))
+    out = errors(amps_c[idx, 0], ref, n_qubits)
+    out["reference"] = f"FP64 state vector of the same circuit (tests/golden/{path})"
+    return out
+
+
+def permutation_check(name, w, net):
+    """For the 6x6 workload: the permutation circuit of the same grid and
+    depth, whose fused network has the same structure (so the plan is
+    unchanged and only leaf data differs), with its exact amplitudes on a
+    subset of the groups (tests/golden/c3_permutation.json)."""
+    if name != "C3":
+        return None
+    from paper_2212_04749_amd.circuit_tn import build_network
+    from workload import permutation_circuit
+    g = json.load(open(os.path.join(GOLDEN, "c3_permutation.json")))
+    pnet = build_network(permutation_circuit(w.grid, w.depth, g["permutation_seed"]))
+    if pnet.indices != net.indices:
+        raise RuntimeError("permutation network differs in structure")
+    return {"net": net, "pnet": pnet, "groups": g["groups"], "ref": _golden_amps(g),
+            "seed": g["permutation_seed"]}
+
+
+def run_leg(api, torch, name, w, net, spec, precision, batch, steps, warmup, args, e=None, check=None,
+            s_range=None, profile_out=""):
+    """One precision on one plan: warm-up passes, then `steps` timed passes
+    (each from an empty stem cache with zeroed amplitudes: every slice of the
+    range, slice-sums and XEB) between HIP events on the plan's stream; the
+    host waits for pass i-1 while pass i is queued, so it reports progress
+    without idling the GPU.  With `check`, the first warm-up pass runs the
+    permutation circuit's leaves and gives the error figure."""
+    import numpy as np
+    words = w.bitstrings()
+    t0 = time.perf_counter()
+    run = api.Contraction(net, spec, words, precision=precision, slice_batch=batch)
+    torch.cuda.synchronize()
+    t_bind = time.perf_counter() - t0
+    t_tune = 0.0
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        autotune(run)
+        t_tune = time.perf_counter() - t0
+    info = run.info
+    log(f"{name} {precision}: bind {t_bind:.2f}s autotune {t_tune:.2f}s workspace "
+        f"{info.workspace_bytes / 2**30:.2f} GiB, {info.n_chunks} key chunks, {info.n_slices} slices")
+    amps = run.new_amplitudes()
+    s_begin, s_end = s_range or (0, run.n_slices)
+    xeb_out = None
+
+    def step():
+        nonlocal xeb_out
+        run.reset_cache()
+        with torch.cuda.stream(run.stream):
+            amps.zero_()
+        run.execute(amps, s_begin, s_end)
+        xeb_out = run.xeb_dev(amps)
+
+    err = None
+    done = 0
+    if check is not None:
+        for t, x in enumerate(check["pnet"].tensors):
+            run.set_tensor(t, x)
+        step()
+        run.synchronize()
+        a = amps.cpu().numpy()
+        blocks = (a[..., 0] + 1j * a[..., 1])[np.array(check["groups"])]
+        err = errors(blocks, check["ref"], w.n_qubits)
+        err["reference"] = (f"exact amplitudes of the permutation circuit (seed {check['seed']}) on the same "
+                            f"network and plan, full pass with its leaves swapped in "
+                            f"(tests/golden/c3_permutation.json, oracle.closed_forms)")
+        for t, x in enumerate(check["net"].tensors):
+            run.set_tensor(t, x)
+        done = 1
+        log(f"{name} {precision}: warm-up pass on the permutation circuit, rel err {err['rel_err']:.2e}")
+    for i in range(max(0, warmup - done)):
+        step()
+        run.synchronize()
+        log(f"{name} {precision}: warm-up {i + done} done")
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    evs[0].record(run.stream)
+    for i in range(steps):
+        step()
+        evs[i + 1].record(run.stream)
+        if i >= 1:
+            evs[i].synchronize()
+            log(f"{name} {precision}: timed pass {i - 1} done")
+    torch.cuda.synchronize()
+    ms_step = evs[0].elapsed_time(evs[steps]) / steps
+    log(f"{name} {precision}: {steps} timed passes, {ms_step:.2f} ms per pass")
+    full = (s_begin, s_end) == (0, run.n_slices)
+    ms_slices = None
+    if not full:
+        # the same slices again with the stem cache kept: the per-slice part
+        # of the step, so that the projection counts the slice-invariant
+        # prologue once for the job
+        with torch.cuda.stream(run.stream):
+            amps.zero_()
+        e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e2.record(run.stream)
+        run.execute(amps, s_begin, s_end)
+        e3.record(run.stream)
+        torch.cuda.synchronize()
+        ms_slices = e2.elapsed_time(e3)
+    a = amps.cpu().numpy()
+    amps_c = a[..., 0] + 1j * a[..., 1]
+    xeb = float(xeb_out.cpu().item()) if full else None
+    if err is None and full:
+        err = reference_error(name, amps_c, w.n_qubits)
+    n_batches = -(-run.n_slices // batch)
+    roof, per, t_roof_ms = roofline(run, precision, n_batches, run.n_slices - (n_batches - 1) * batch, name)
+    if profile_out:
+        write_profile(profile_out, run, spec, net, w, batch, per)
+    n_timed = s_end - s_begin
+    frac = n_timed / run.n_slices
+    if full:
+        secs = ms_step / 1e3
+    else:
+        secs = (max(0.0, ms_step - ms_slices) + ms_slices / n_timed * run.n_slices) / 1e3
+    cmac_timed = info.cmac_invariant + (info.cmac_total - info.cmac_invariant) * frac
+    tflops = 8 * cmac_timed / (ms_step / 1e3) / 1e12
+    out = {
+        "dtype": PRECISION_NAME[precision],
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": ms_step,
+        "value": info.n_amplitudes / secs,
+        "unit": "amplitudes/s",
+        "complex_tflops": tflops,
+        # whole-step rate over the MFMA peak of the precision's arithmetic
+        "mfma_peak_frac": tflops / PEAK_TFLOPS["fp32" if precision == "c64" else "fp16"],
+        # sum over the steps of each one's roofline time (the larger of its
+        # flops over the MFMA peak of its kernel and its algorithmic bytes
+        # over 8 TB/s), over the measured (or, for a slice subset, projected) time
+        "step_roofline_ms": t_roof_ms,
+        "step_roofline_frac": t_roof_ms / (secs * 1e3),
+        "xeb": xeb,
+        "error_vs_fp64": err,
+        "bind_s": t_bind,
+        "autotune_s": t_tune,
+        "config": workload_description(name, w, info, spec, e) | {"slice_batch": batch, "precision": precision,
+                                                                     "key_chunks": int(info.n_chunks)}
+        | ({} if full else {"slices_timed": [s_begin, s_end], "value_is_projected": True,
+                            "projected_job_s": secs, "per_slice_ms": ms_slices / n_timed,
+                            "prologue_ms": max(0.0, ms_step - ms_slices)}),
+        "roofline": roof,
+    }
+    run.close()
+    del amps
+    torch.cuda.empty_cache()
+    return out
+
+
+def write_profile(path, run, spec, net, w, batch, per):
+    from paper_2212_04749_amd import planner as P
+    st = P.Structure.from_network(net, w.open_qubits)
+    smask = sum(1 << i for i in spec.sliced)
+    tree = P.build_tree(st, spec.pairs, smask)
+    wid = P.widths(P.build_tree(st, spec.pairs), w.bitstrings())
+    prof = run.profile(0, min(batch, run.n_slices))
+    steps = []
+    for j, ((ms, kid, cm, by), dep) in enumerate(zip(prof, run.step_dep())):
+        a, b_ = spec.pairs[j]
+        ma, mb = tree.masks[a], tree.masks[b_]
+        if mb.bit_count() > ma.bit_count():
+            ma, mb = mb, ma
+        k_ = (ma & mb).bit_count()
+        steps.append({"step": j, "ms": ms, "kernel": kid, "cmac": cm, "bytes": by, "dep": dep,
+                      "m": ma.bit_count() - k_, "n": mb.bit_count() - k_, "k": k_,
+                      "w": wid[st.n_tensors + j]})
+    with open(path, "w") as f:
+        json.dump({"per_kernel": {str(k): v for k, v in per.items()}, "steps": steps}, f, indent=1)
+
+
+def cpu_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model
+
+
+def blas_threads() -> int:
+    try:
+        from threadpoolctl import threadpool_info
+        n = [i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas"]
+        if n:
+            return int(max(n))
+    except Exception:
+        pass
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_baseline_sv(w):
+    """The oracle's plain-C FP64 state vector (oracle/sv.c) over the whole
+    circuit for the workload's whole batch, timed (n <= 30 qubits)."""
+    from oracle import sv_native
+    circ, words = w.circuit(), w.bitstrings()
+    t0 = time.perf_counter()
+    sv_native.amplitudes(circ, words)
+    t = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    return {"value": w.k / t, "unit": "amplitudes/s", "cores": cores, "kind": "oracle", "cpu_model": cpu_info(),
+            "sample": f"the whole job: FP64 state vector (oracle/sv.c) of the {w.n_qubits}-qubit circuit and all "
+                      f"{w.k} amplitudes, {t:.1f} s, not extrapolated"}
+
+
+def cpu_baseline_tn(w, cap: int = 25, seed: int = 2025, min_s: float = 10.0, max_slices: int = 8):
+    """The oracle's plain tensor-network contraction (oracle/tn.py: unfused
+    network, its own greedy order, numpy tensordot in complex128), sliced by
+    its own slicer to rank `cap` so that one slice is a bounded sample;
+    seeded (group, slice) contractions are timed until at least min_s
+    seconds of work, and the whole-job time is their mean x the oracle's
+    slice count x the number of groups (every slice of every group is the
+    same contraction with other values)."""
+    import numpy as np
+    from oracle import tn as otn
+    from oracle.circuit import words_to_bits
+    circ, words = w.circuit(), w.bitstrings()
+    plan = otn.Plan(circ, w.open_qubits, cap)
+    rng = np.random.default_rng(seed)
+    times = []
+    while len(times) < max_slices and sum(times) < min_s:
+        g = int(rng.integers(0, len(words)))
+        assignment = [int(x) for x in rng.integers(0, 2, len(plan.sliced))]
+        bits = words_to_bits(words[g:g + 1], plan.net.n)[0]
+        t0 = time.perf_counter()
+        plan.slice_partial(bits, assignment)
+        times.append(time.perf_counter() - t0)
+    t = sum(times) / len(times)
+    n_sl = 2 ** len(plan.sliced)
+    job_s = t * n_sl * len(words)
+    amps = len(words) << len(w.open_qubits)
+    return {"value": amps / job_s, "unit": "amplitudes/s", "cores": blas_threads(), "kind": "oracle",
+            "cpu_model": cpu_info(),
+            "sample": f"{len(times)} of the oracle tensor network's {n_sl} slices (its own greedy order and slicer "
+                      f"at rank {cap}) of seeded groups among the {len(words)} bitstring groups (2^"
+                      f"{len(w.open_qubits)} amplitudes each), {sum(times):.1f} s in all, {t:.2f} s per slice, "
+                      f"scaled by {n_sl} slices x {len(words)} groups to {job_s:.3g} s for the whole job"}
 
 
 def roofline(run, precision, n_batches, nb_last, workload):
@@ -231,81 +507,15 @@ def pmc_traffic(workload: str, precision: str, kernel_id: int, step: int):
     return None
 
 
-def cpu_baseline(name, w):
-    """The oracle (plain-C FP64 state vector) on a bounded sample: the set-up
-    and the first G_s gates are timed and the full-circuit time is
-    extrapolated linearly in the gate count; the oracle's amplitudes/s for
-    this workload is k over that time."""
-    from oracle import sv_native
-    from oracle.circuit import gate_list
-    circ, words = w.circuit(), w.bitstrings()
-    if w.n_qubits > 30:
-        return None
-    n, glist = gate_list(circ)
-    t0 = time.perf_counter()
-    sv_native.amplitudes(circ, words, max_gates=0)
-    t_setup = time.perf_counter() - t0
-    gs = min(len(glist), 60)
-    t0 = time.perf_counter()
-    sv_native.amplitudes(circ, words, max_gates=gs)
-    t_sample = time.perf_counter() - t0
-    per_gate = max(t_sample - t_setup, 1e-9) / gs
-    t_full = t_setup + per_gate * len(glist)
-    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
-    return {"value": w.k / t_full, "unit": "amplitudes/s", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 state vector (oracle/sv.c) of the same {w.n_qubits}-qubit circuit: set-up plus the "
-                      f"first {gs} of {len(glist)} gates timed ({t_sample:.1f} s), full run extrapolated to "
-                      f"{t_full:.1f} s for all {w.k} bitstrings"}
-
-
-GROUP_EST_S = 30.0
-
-
-def run_in_parts(api, w, e, net, prec, need, stream, args, gi):
-    """One plan too large for a bounded queue pass: its slices run in
-    parts of about GROUP_EST_S estimated seconds, each timed with HIP events
-    and reported when it ends; the pass starts from an empty stem cache, so
-    the parts add up to one complete contraction."""
-    import math
-    import torch
-    spec = api.PlanSpec([tuple(x) for x in e["pairs"]], e["sliced"], (), e["cap"])
-    r = api.Contraction(net, spec, w.bitstrings(), precision=prec, slice_batch=1, stream=stream,
-                        memory_budget=need)
-    n = r.n_slices
-    parts = min(n, max(1, math.ceil(e["est_seconds"] / GROUP_EST_S)))
-    bounds = [n * i // parts for i in range(parts + 1)]
-    log(f"group {gi}: {w.name} alone, estimated {e['est_seconds']:.1f} s per pass, {n} slices in {parts} parts")
-    amps = None
-    for rep in range(args.warmup + args.steps):
-        timed = rep >= args.warmup
-        r.reset_cache()
-        amps = r.new_amplitudes() if amps is None else amps.zero_()
-        ms = 0.0
-        for i in range(parts):
-            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            ev0.record(stream)
-            r.execute(amps, bounds[i], bounds[i + 1])
-            ev1.record(stream)
-            stream.synchronize()
-            ms += ev0.elapsed_time(ev1)
-            log(f"group {gi}: {'timed' if timed else 'warm-up'} pass {rep}, slices [{bounds[i]}, {bounds[i + 1]}) "
-                f"done, {ms / 1e3:.1f} s so far")
-    x = r.xeb(amps)
-    out = (ms, x, r.k, r.info.cmac_total)
-    r.close()
-    return out
-
-
 def run_uneven(args) -> None:
     """The uneven batch: the 32 seeded circuits of workload.configs with the
-    stored plans (plans/c5_cap30.json), in complex-half by default. Plans
-    are packed, largest workspace first, into groups whose workspaces fit
-    the device memory; each group is one queue (one captured graph of all
-    of its plans' launches, slice-sums and XEBs). The timed step replays
-    every group's queue once; amplitudes/s counts every amplitude of every
-    circuit in the batch."""
+    stored plans (plans/c5_cap30.json), complex-half by default, as ONE queue
+    bound to one workspace (every plan's static region plus one arena shared
+    by all, matnc_queue_bind) and captured as one graph: every plan's stem,
+    slices, slice-sums and XEB.  The timed step replays that graph once;
+    amplitudes/s counts every amplitude of every circuit."""
     import torch
-    from paper_2212_04749_amd import api, binding as B
+    from paper_2212_04749_amd import api
     from paper_2212_04749_amd.circuit_tn import build_network
     from paper_2212_04749_amd.plans import make_c5
     from workload.configs import uneven_batch_c5
@@ -317,139 +527,112 @@ def run_uneven(args) -> None:
         e = plans[w.name]
         (sel if e["est_seconds"] <= args.max_est_s else skipped).append((w, e))
     free, _ = torch.cuda.mem_get_info()
-    cap_bytes = int(0.85 * free)
-    # workspace each plan needs (chunked down to the device budget if larger)
-    items = []
-    for w, e in sel:
-        net = build_network(w.circuit())
-        ranks, ids, data = api.network_arrays(net)
-        h = B.matnc_network_create(ranks, ids, data, net.n_qubits, net.output_index)
-        p = B.matnc_plan_create(h, [tuple(x) for x in e["pairs"]], e["sliced"], [], w.bitstrings(),
-                                api.PRECISIONS[prec], e["cap"], 1, cap_bytes)
-        need = int(B.matnc_plan_info(p).workspace_bytes)
-        B.matnc_plan_destroy(p)
-        B.matnc_network_destroy(h)
-        items.append((need, w, e, net))
-    items.sort(key=lambda x: -x[0])
-    # first fit, largest workspace first; a group also stays under about
-    # GROUP_EST_S of estimated work so that each pass over it reports back
-    # within a bounded time (a single larger plan gets a group of its own)
-    groups = []
-    for it in items:
-        est = it[2]["est_seconds"]
-        for g in groups:
-            if g["bytes"] + it[0] <= cap_bytes and g["est"] + est <= GROUP_EST_S:
-                g["items"].append(it)
-                g["bytes"] += it[0]
-                g["est"] += est
-                break
-        else:
-            groups.append({"bytes": it[0], "est": est, "items": [it]})
-    log(f"uneven batch: {len(sel)} circuits in {len(groups)} queue groups, {len(skipped)} left out "
-        f"(estimated over {args.max_est_s} s each)")
-    total_ms = 0.0
-    xebs, n_amps, cmac = {}, 0, 0.0
+    budget = int(0.75 * free)
     stream = torch.cuda.Stream()
-    for gi, g in enumerate(groups):
-        if len(g["items"]) == 1 and g["est"] > GROUP_EST_S:
-            need, w, e, net = g["items"][0]
-            ms, x, k, cm = run_in_parts(api, w, e, net, prec, need, stream, args, gi)
-            total_ms += ms
-            xebs[w.name] = x
-            n_amps += k
-            cmac += cm
-            torch.cuda.empty_cache()
-            continue
-        runs = []
-        for need, w, e, net in g["items"]:
-            spec = api.PlanSpec([tuple(x) for x in e["pairs"]], e["sliced"], (), e["cap"])
-            runs.append(api.Contraction(net, spec, w.bitstrings(), precision=prec, slice_batch=1, stream=stream,
-                                        memory_budget=need))
-        q = api.Queue(runs)
-        log(f"group {gi}: {len(runs)} circuits ({', '.join(it[1].name for it in g['items'])}), "
-            f"estimated {g['est']:.1f} s per pass; capturing")
-        t0 = time.perf_counter()
-        amps, xeb = q.execute()  # capture
+    runs = []
+    for w, e in sel:
+        spec = api.PlanSpec([tuple(x) for x in e["pairs"]], e["sliced"], (), e["cap"])
+        runs.append(api.Contraction(build_network(w.circuit()), spec, w.bitstrings(), precision=prec, slice_batch=1,
+                                    stream=stream, memory_budget=budget, bind=False))
+    q = api.Queue(runs, shared=True)
+    log(f"uneven batch: {len(runs)} circuits in one queue, shared workspace {q.workspace.numel() / 2**30:.1f} GiB "
+        f"(the plans' own workspaces add up to {sum(r.info.workspace_bytes for r in runs) / 2**30:.1f} GiB), "
+        f"{len(skipped)} left out (estimated over {args.max_est_s} s each)")
+    t0 = time.perf_counter()
+    amps, xeb = q.execute()  # captures the queue's graph; the first warm-up pass
+    stream.synchronize()
+    log(f"capture and first pass {time.perf_counter() - t0:.1f} s")
+    for i in range(max(0, args.warmup - 1)):
+        q.execute(amps, xeb)
         stream.synchronize()
-        log(f"group {gi}: first pass {time.perf_counter() - t0:.1f} s")
-        for _ in range(args.warmup):
-            q.execute(amps, xeb)
-            stream.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
-        for _ in range(args.steps):
-            q.execute(amps, xeb)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / args.steps
-        total_ms += ms
-        xs = xeb.cpu().numpy()
-        for (need, w, e, net), r, x in zip(g["items"], runs, xs):
-            xebs[w.name] = float(x)
-            n_amps += r.k
-            cmac += r.info.cmac_total
-        log(f"group {gi}: {len(runs)} circuits, {g['bytes'] / 2**30:.1f} GiB, {ms:.2f} ms per pass")
-        q.close()
-        for r in runs:
-            r.close()
-        del amps, xeb
-        torch.cuda.empty_cache()
+        log(f"warm-up pass {i + 1} done")
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record(stream)
+    for i in range(args.steps):
+        q.execute(amps, xeb)
+        evs[i + 1].record(stream)
+        if i >= 1:
+            evs[i].synchronize()
+            log(f"timed pass {i - 1} done")
+    torch.cuda.synchronize()
+    total_ms = evs[0].elapsed_time(evs[args.steps]) / args.steps
+    xs = xeb.cpu().numpy()
+    xebs = {w.name: float(x) for (w, _), x in zip(sel, xs)}
+    n_amps = sum(r.k for r in runs)
+    cmac = sum(r.info.cmac_total for r in runs)
     secs = total_ms / 1e3
     out = {
-        "metric": "sustained complex TFLOP/s + amplitudes/sec per slice-batch at stated err vs FP64",
+        "metric": METRIC,
         "value": n_amps / secs, "unit": "amplitudes/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": total_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "complex64" if prec == "c64" else "complex-half", "data": "synthetic",
+        "dtype": PRECISION_NAME[prec], "data": "synthetic",
         "complex_tflops": 8 * cmac / secs / 1e12,
         "config": {"workload": f"C5: uneven batch of {len(sel)} seeded grid RQCs (20-36 qubits, depth 10-16, "
-                               f"256-4096 bitstrings), stored plans at rank cap 30, one queue per memory group",
-                   "circuits": len(sel), "left_out": [w.name for w, _ in skipped], "groups": len(groups),
+                               f"256-4096 bitstrings), stored plans at rank cap 30, one queue, one workspace, "
+                               f"one graph",
+                   "circuits": len(sel), "left_out": [w.name for w, _ in skipped],
+                   "shared_workspace_bytes": int(q.workspace.numel()),
                    "amplitudes": n_amps, "precision": prec},
         "xeb_per_circuit": xebs,
     }
+    q.close()
+    for r in runs:
+        r.close()
     print(json.dumps(out), flush=True)
 
 
-def beside_pass(api, torch, net, spec, words, name, batch, args):
-    """The same workload and plan in complex-half, timed with the same
-    protocol (every step a full pass from an empty stem cache), for the
-    complex-half rate beside the complex64 one."""
-    run = api.Contraction(net, spec, words, precision="chalf", slice_batch=batch)
-    if not args.no_autotune:
-        autotune(run)
-    amps = run.new_amplitudes()
-
-    def step():
-        run.reset_cache()
-        with torch.cuda.stream(run.stream):
-            amps.zero_()
-        run.execute(amps)
-        return run.xeb_dev(amps)
-
-    for _ in range(args.warmup):
-        step()
-        run.synchronize()
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(run.stream)
-    for _ in range(args.steps):
-        x = step()
-    ev1.record(run.stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
-    log(f"complex-half beside: {ms:.2f} ms/step")
-    a = amps.cpu().numpy()
-    err = reference_error(name, run, a[..., 0] + 1j * a[..., 1])
-    n_batches = -(-run.n_slices // batch)
-    roof, _, t_roof_ms = roofline(run, "chalf", n_batches, run.n_slices - (n_batches - 1) * batch, name)
-    info = run.info
-    tflops = 8 * info.cmac_total / (ms / 1e3) / 1e12
-    out = {"dtype": "complex-half", "ms_per_step": ms, "value": info.n_amplitudes / (ms / 1e3),
-           "unit": "amplitudes/s", "complex_tflops": tflops, "mfma_peak_frac": tflops / PEAK_TFLOPS["fp16"],
-           "step_roofline_frac": t_roof_ms / ms, "xeb": float(x.cpu().item()), "error_vs_fp64": err,
-           "roofline": roof}
-    run.close()
-    return out
+def run_fidelity(args) -> None:
+    """The fidelity workload (main text Eq. (2), Fig. 4): bitstrings of a
+    20-qubit circuit sampled from the mixture of its exact distribution
+    (weight F) and the uniform one, stored with their exact x = 2^n p
+    (tests/golden/pt_samples.json, written by the oracle).  Their amplitudes
+    are computed on the GPU in both precisions; F is estimated by the linear
+    XEB (on the GPU) and by maximum likelihood under Eq. (2); the histogram
+    of x against Eq. (2)'s density at the fitted F is the data of Fig. 4."""
+    import numpy as np
+    import torch
+    from paper_2212_04749_amd import analysis, api
+    from workload import GridSpec, random_circuit
+    g = json.load(open(os.path.join(GOLDEN, "pt_samples.json")))
+    circ = random_circuit(GridSpec(*g["grid"]), g["depth"], g["circuit_seed"])
+    n = g["n_qubits"]
+    sets = []
+    for st in g["sets"]:
+        words = np.array([int(x) for x in st["words"]], dtype=np.uint64)
+        x_ref = np.array(st["x"])
+        entry = {"fidelity": st["fidelity"], "samples": len(words),
+                 "expected_linear_xeb": st["fidelity"] * g["ideal_linear_xeb"]}
+        for prec in ("c64", "chalf"):
+            run = api.Contraction.from_circuit(circ, words, cap=18, precision=prec, slice_batch=2, trials=4)
+            amps = run.execute()
+            run.synchronize()
+            torch.cuda.synchronize()
+            evs = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            evs[0].record(run.stream)
+            for _ in range(max(1, args.steps)):
+                run.reset_cache()
+                with torch.cuda.stream(run.stream):
+                    amps.zero_()
+                run.execute(amps)
+            evs[1].record(run.stream)
+            torch.cuda.synchronize()
+            ms = evs[0].elapsed_time(evs[1]) / max(1, args.steps)
+            f_lin = run.xeb(amps)
+            a = amps.cpu().numpy()
+            x = analysis.x_values(a[:, 0, 0] + 1j * a[:, 0, 1], n)
+            f_mle = analysis.fit_fidelity(x)
+            entry[PRECISION_NAME[prec]] = {
+                "linear_xeb_gpu": f_lin, "mle_fidelity": f_mle, "ms_per_pass": ms,
+                "amplitudes_per_s": len(words) / (ms / 1e3),
+                "x_rel_err": float(np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)),
+                "histogram": analysis.porter_thomas_histogram(x, f_mle, bins=24, x_max=6.0)}
+            run.close()
+            log(f"F = {st['fidelity']} {prec}: linear XEB {f_lin:.4f}, MLE {f_mle:.4f}, {ms:.2f} ms per pass")
+        sets.append(entry)
+    print(json.dumps({"workload": "PT: 4x5 grid RQC (20 qubits), depth 12, 4096 bitstrings per fidelity sampled "
+                                  "from the mixture of the exact distribution and the uniform one",
+                      "sets": sets}), flush=True)
 
 
 def main():
@@ -466,187 +649,92 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
-    if args.workload == "C5":
+    name = args.workload
+    if args.precision is None:
+        args.precision = "chalf" if name in ("C3", "C4", "C5") else "c64"
+    if name == "C5":
         run_uneven(args)
+        return
+    if name == "PT":
+        run_fidelity(args)
         return
     from paper_2212_04749_amd import api, planner
     from paper_2212_04749_amd.circuit_tn import build_network
     from workload import CONFIGS
 
-    name = args.workload
     w = CONFIGS[name]
     batch = args.slice_batch or {"C1": 1, "C2": 4, "C3": 8, "C4": 1}[name]
-    circ, words = w.circuit(), w.bitstrings()
+    words = w.bitstrings()
     t0 = time.perf_counter()
-    net = build_network(circ)
-    cap = w.cap if w.cap is not None else 32
-    # at least the workload's slice count; a cheaper plan that needs more
-    # sliced indices to meet the rank cap keeps its real count
-    pt = args.partition_trials if args.partition_trials >= 0 else (16 if name in ("C3", "C4") else 0)
-    if name in ("C3", "C4") and not args.replan:
-        # the stored plan (plans/make_c3.py, make_c4.py: minutes to tens of
-        # minutes of host planning)
-        import importlib
-        e = importlib.import_module(f"paper_2212_04749_amd.plans.make_{name.lower()}").load()
-        pairs = [tuple(x) for x in e["pairs"]]
-        st0 = planner.Structure.from_network(net, w.open_qubits)
-        plan = planner.Plan(pairs, list(e["sliced"]), planner.costs(
-            st0, planner.build_tree(st0, pairs, sum(1 << i for i in e["sliced"])),
-            planner.widths(planner.build_tree(st0, pairs), words), sum(1 << i for i in e["sliced"])),
-            planner.widths(planner.build_tree(st0, pairs), words), "stored:" + e["method"])
+    net = build_network(w.circuit())
+    e = None
+    if name in ("C2", "C3", "C4") and not args.replan:
+        plan, e = stored_plan(name, net, words, w.open_qubits)
         cap = e["cap"]
     else:
+        cap = w.cap if w.cap is not None else 32
+        pt = args.partition_trials if args.partition_trials >= 0 else (16 if name in ("C3", "C4") else 0)
         plan = planner.find_plan(net, words, w.open_qubits, w.cap, seed=0, trials=args.trials, partition_trials=pt,
                                  min_slices=w.n_slices_target.bit_length() - 1 if w.n_slices_target else 0,
                                  progress=lambda msg: log(f"planning: {msg}"))
     spec = api.PlanSpec(plan.pairs, plan.sliced, tuple(w.open_qubits), cap, plan.method)
     t_plan = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    run = api.Contraction(net, spec, words, precision=args.precision, slice_batch=batch)
-    torch.cuda.synchronize()
-    t_bind = time.perf_counter() - t0
-    t_tune = 0.0
-    if not args.no_autotune:
-        t0 = time.perf_counter()
-        autotune(run)
-        t_tune = time.perf_counter() - t0
-    info = run.info
-    log(f"plan {t_plan:.2f}s bind {t_bind:.2f}s autotune {t_tune:.2f}s workspace {info.workspace_bytes / 2**30:.2f} GiB "
-        f"slices {info.n_slices} cmac_total {info.cmac_total:.3e}")
+    check = permutation_check(name, w, net)
+    s_range = None
+    if args.slice_subset:
+        n_sl = 2 ** len(plan.sliced)
+        if args.slice_subset < n_sl:
+            rng = np.random.default_rng(2004)
+            n_sub = -(-args.slice_subset // batch) * batch
+            s0 = int(rng.integers(0, (n_sl - n_sub) // batch + 1)) * batch
+            s_range = (s0, min(n_sl, s0 + n_sub))
+            log(f"timing slices [{s_range[0]}, {s_range[1]}) of {n_sl}")
 
-    amps = run.new_amplitudes()
-    xeb_out = None
-    s_begin, s_end = 0, run.n_slices
-    if args.slice_subset and args.slice_subset < run.n_slices:
-        rng = np.random.default_rng(2004)
-        n_sub = -(-args.slice_subset // batch) * batch
-        s_begin = int(rng.integers(0, (run.n_slices - n_sub) // batch + 1)) * batch
-        s_end = min(run.n_slices, s_begin + n_sub)
-        log(f"timing slices [{s_begin}, {s_end}) of {run.n_slices}")
-
-    def step():
-        nonlocal xeb_out
-        run.reset_cache()
-        with torch.cuda.stream(run.stream):
-            amps.zero_()
-        run.execute(amps, s_begin, s_end)
-        xeb_out = run.xeb_dev(amps)
-
-    for i in range(args.warmup):
-        step()
-        run.synchronize()
-        log(f"warmup {i} done")
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(run.stream)
-    for i in range(args.steps):
-        step()
-    ev1.record(run.stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    log(f"timed {args.steps} steps: {ms_step:.2f} ms/step (wall {wall / args.steps * 1e3:.2f} ms/step)")
-    full = (s_begin, s_end) == (0, run.n_slices)
-    ms_slices = None
-    if not full:
-        # the same slices again with the stem cache kept: the per-slice part
-        # of the step, so that the projection counts the slice-invariant
-        # prologue once for the job
-        with torch.cuda.stream(run.stream):
-            amps.zero_()
-        ev2, ev3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev2.record(run.stream)
-        run.execute(amps, s_begin, s_end)
-        ev3.record(run.stream)
-        torch.cuda.synchronize()
-        ms_slices = ev2.elapsed_time(ev3)
-        log(f"slices [{s_begin}, {s_end}) with the stem cache kept: {ms_slices:.2f} ms "
-            f"({ms_slices / (s_end - s_begin):.2f} ms per slice)")
-
-    amps_np = amps.cpu().numpy()
-    amps_c = amps_np[..., 0] + 1j * amps_np[..., 1]
-    xeb = float(xeb_out.cpu().item()) if full else None
-    err = reference_error(name, run, amps_c) if full else None
-    n_batches = -(-run.n_slices // batch)
-    roof, per, t_roof_ms = roofline(run, args.precision, n_batches, run.n_slices - (n_batches - 1) * batch, name)
-    if args.profile_out:
-        from paper_2212_04749_amd import planner as P
-        st = P.Structure.from_network(net, w.open_qubits)
-        smask = sum(1 << i for i in spec.sliced)
-        tree = P.build_tree(st, spec.pairs, smask)
-        prof = run.profile(0, min(batch, run.n_slices))
-        steps = []
-        for j, ((ms, kid, cm, by), dep) in enumerate(zip(prof, run.step_dep())):
-            a, b_ = spec.pairs[j]
-            ma, mb = tree.masks[a], tree.masks[b_]
-            if mb.bit_count() > ma.bit_count():
-                ma, mb = mb, ma
-            k_ = (ma & mb).bit_count()
-            steps.append({"step": j, "ms": ms, "kernel": kid, "cmac": cm, "bytes": by, "dep": dep,
-                          "m": ma.bit_count() - k_, "n": mb.bit_count() - k_, "k": k_,
-                          "w": plan.widths[st.n_tensors + j]})
-        with open(args.profile_out, "w") as f:
-            json.dump({"per_kernel": {str(k): v for k, v in per.items()}, "steps": steps}, f, indent=1)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        try:
-            cpu = cpu_baseline(name, w)
-        except MemoryError:
-            cpu = None
-    # a slice subset is projected to the whole job: the slice-invariant
-    # prologue once, the per-slice work for every slice
-    n_timed = s_end - s_begin
-    frac = n_timed / run.n_slices
-    if full:
-        secs = ms_step / 1e3
-    else:
-        prologue_ms = max(0.0, ms_step - ms_slices)
-        secs = (prologue_ms + ms_slices / n_timed * run.n_slices) / 1e3
-    cmac_timed = info.cmac_invariant + (info.cmac_total - info.cmac_invariant) * frac
+    head = run_leg(api, torch, name, w, net, spec, args.precision, batch, args.steps, args.warmup, args, e,
+                   check, s_range, args.profile_out)
     out = {
-        "metric": "sustained complex TFLOP/s + amplitudes/sec per slice-batch at stated err vs FP64",
-        "value": info.n_amplitudes / secs,
+        "metric": METRIC,
+        "value": head["value"],
         "unit": "amplitudes/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "complex64" if args.precision == "c64" else "complex-half",
+        "dtype": head["dtype"],
         "data": "synthetic",
-        "complex_tflops": 8 * cmac_timed / (ms_step / 1e3) / 1e12,
-        # whole-step rate over the MFMA peak of the precision (FP32 for
-        # complex64, FP16 for complex-half, whose stem still runs on FP32)
-        "mfma_peak_frac": 8 * cmac_timed / (ms_step / 1e3) / 1e12 /
-                          PEAK_TFLOPS["fp32" if args.precision == "c64" else "fp16"],
-        # sum over the steps of each one's roofline time (the larger of its
-        # flops over the MFMA peak of its kernel and its algorithmic bytes
-        # over 8 TB/s), over the measured step time
-        # (for a slice subset both are whole-job figures: the projected time)
-        "step_roofline_ms": t_roof_ms,
-        "step_roofline_frac": t_roof_ms / (secs * 1e3),
-        "xeb": xeb,
-        "error_vs_fp64": err,
-        "plan_s": t_plan,
-        "bind_s": t_bind,
-        "autotune_s": t_tune,
-        "config": workload_description(name, w, info, spec) | {"slice_batch": batch, "precision": args.precision}
-        | ({} if full else {"slices_timed": [s_begin, s_end], "value_is_projected": True,
-                            "projected_job_s": secs, "per_slice_ms": ms_slices / n_timed,
-                            "prologue_ms": max(0.0, ms_step - ms_slices)}),
-        "roofline": roof,
-        "cpu_baseline": cpu,
     }
-    run.close()
-    if args.precision == "c64" and full and not args.no_beside and (args.beside or name in ("C1", "C2")):
-        torch.cuda.empty_cache()
-        out["complex_half"] = beside_pass(api, torch, net, spec, words, name, batch, args)
+    out |= {k: head[k] for k in ("complex_tflops", "mfma_peak_frac", "step_roofline_ms", "step_roofline_frac",
+                                 "xeb", "error_vs_fp64", "bind_s", "autotune_s")}
+    out["plan_s"] = t_plan
+    out["config"] = head["config"]
+    out["roofline"] = head["roofline"]
+    out["cpu_baseline"] = None
+    other = "c64" if args.precision == "chalf" else "chalf"
+    if args.beside_steps > 0:
+        leg = run_leg(api, torch, name, w, net, spec, other, batch, args.beside_steps, 1, args, e, check, s_range)
+        leg.pop("config")
+        out["beside"] = {PRECISION_NAME[other]: leg}
+    if name == "C3" and not args.no_secondary:
+        # the 5x6 workload (4096 bitstrings, stored plan) in both precisions
+        w2 = CONFIGS["C2"]
+        net2 = build_network(w2.circuit())
+        plan2, e2 = stored_plan("C2", net2, w2.bitstrings(), ())
+        spec2 = api.PlanSpec(plan2.pairs, plan2.sliced, (), e2["cap"], plan2.method)
+        sec = {}
+        for prec in ("c64", "chalf"):
+            sec[PRECISION_NAME[prec]] = run_leg(api, torch, "C2", w2, net2, spec2, prec, 4, 3, 1, args, e2)
+        out["secondary"] = {"C2": sec}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        t0 = time.perf_counter()
+        try:
+            out["cpu_baseline"] = cpu_baseline_sv(w) if w.n_qubits <= 30 else cpu_baseline_tn(w)
+        except MemoryError:
+            out["cpu_baseline"] = None
+        log(f"cpu baseline: {time.perf_counter() - t0:.1f} s")
     print(json.dumps(out), flush=True)
 
 
