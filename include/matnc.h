@@ -132,27 +132,25 @@ int matnc_plan_create(matnc_network net, const int *pairs, int n_sliced,
  * matnc_plan_create_ex -- matnc_plan_create with its tuning choices in a
  * struct (zero-initialise it, then set the fields):
  *   slice_batch, memory_budget   as in matnc_plan_create
- *   half_extra                   complex-half plans: besides the tensors of
- *                                the twig (reuse width >= a quarter of the
- *                                distinct bitstrings), the number of other
- *                                intermediates stored in FP16 -- those whose
- *                                steps carry the most estimated FP32 time,
- *                                which then run on the FP16 MFMA kernels.
- *                                Each adds one FP16 rounding (relative rms
- *                                about 2^-11/sqrt(3)) common to every
- *                                amplitude; -1 = library default (8 for
- *                                batches of at least 4096 amplitudes, k *
- *                                2^n_open, else 0: the linear XEB of K
- *                                amplitudes moves by about a few times the
- *                                relative error over sqrt(K)), 0 = the twig
- *                                only.  Ignored for MATNC_C64.
+ *   half_nodes                   complex-half plans: how many intermediates
+ *                                are stored in FP16 -- those whose steps
+ *                                carry the most estimated FP32 time, which
+ *                                then run on the FP16 MFMA kernels.  Each
+ *                                adds one FP16 rounding (relative rms about
+ *                                2^-11/sqrt(3)) to the amplitudes, so this is
+ *                                the plan's precision budget; 0 keeps every
+ *                                tensor in FP32; -1 = library default,
+ *                                min(28, K / 282) for K = k * 2^n_open
+ *                                amplitudes (the linear XEB of K amplitudes
+ *                                moves by about 2 e / sqrt(K) for relative
+ *                                errors of rms e).  Ignored for MATNC_C64.
  * Errors: as matnc_plan_create; MATNC_E_INVALID for a null opts or
- * half_extra < -1.
+ * half_nodes < -1.
  */
 typedef struct {
   int slice_batch;
   size_t memory_budget;
-  int half_extra;
+  int half_nodes;
 } matnc_plan_options_t;
 
 int matnc_plan_create_ex(matnc_network net, const int *pairs, int n_sliced,

@@ -53,11 +53,11 @@ class Contraction:
 
     def __init__(self, net: TensorNetwork, spec: PlanSpec, words, precision: str = "c64",
                  slice_batch: int = 1, stream=None, device: str = "cuda", memory_budget: Optional[int] = None,
-                 half_extra: int = -1, bind: bool = True):
+                 half_nodes: int = -1, bind: bool = True):
         """memory_budget: largest workspace in bytes (None: 90% of the device
         memory free now); above it the bitstrings are processed in chunks.
-        half_extra: complex-half plans, FP16-stored intermediates outside the
-        twig (-1: the library's default; see matnc_plan_create_ex).
+        half_nodes: complex-half plans, how many intermediates are stored in
+        FP16 (-1: the library's default; see matnc_plan_create_ex).
         bind=False: create the plan only; a Queue(shared=True) binds it."""
         import torch
 
@@ -78,7 +78,7 @@ class Contraction:
         try:
             self._plan = B.matnc_plan_create_ex(self._net, spec.pairs, spec.sliced, list(spec.open_qubits),
                                                 self.words, PRECISIONS[precision], spec.cap, slice_batch,
-                                                memory_budget, half_extra)
+                                                memory_budget, half_nodes)
             self.info = B.matnc_plan_info(self._plan)
             self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
             self.workspace = None
@@ -102,13 +102,13 @@ class Contraction:
     def from_circuit(cls, circ: dict, words, open_qubits: Sequence[int] = (), cap: Optional[int] = None,
                      precision: str = "c64", slice_batch: int = 1, seed: int = 0, trials: int = 32,
                      exact_slices: Optional[int] = None, stream=None, device: str = "cuda",
-                     memory_budget: Optional[int] = None, half_extra: int = -1):
+                     memory_budget: Optional[int] = None, half_nodes: int = -1):
         net = build_network(circ)
         plan = planner.find_plan(net, words, open_qubits, cap, seed=seed, trials=trials,
                                  exact_slices=exact_slices)
         spec = PlanSpec(plan.pairs, plan.sliced, tuple(sorted(open_qubits)),
                         cap if cap is not None else 32, plan.method)
-        return cls(net, spec, words, precision, slice_batch, stream, device, memory_budget, half_extra)
+        return cls(net, spec, words, precision, slice_batch, stream, device, memory_budget, half_nodes)
 
     # ------------------------------------------------------------------
     def new_amplitudes(self):

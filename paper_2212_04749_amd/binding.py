@@ -178,15 +178,15 @@ def matnc_plan_create(net: int, pairs, sliced_ids, open_qubits, bitstrings, prec
 
 
 class PlanOptions(ctypes.Structure):
-    _fields_ = [("slice_batch", c_int), ("memory_budget", c_size_t), ("half_extra", c_int)]
+    _fields_ = [("slice_batch", c_int), ("memory_budget", c_size_t), ("half_nodes", c_int)]
 
 
 def matnc_plan_create_ex(net: int, pairs, sliced_ids, open_qubits, bitstrings, precision: int, max_rank: int,
-                         slice_batch: int = 1, memory_budget: int = 0, half_extra: int = -1) -> int:
+                         slice_batch: int = 1, memory_budget: int = 0, half_nodes: int = -1) -> int:
     out = c_void_p()
     flat = [x for p in pairs for x in p]
     words, pwords = u64_array(bitstrings)
-    opts = PlanOptions(int(slice_batch), int(memory_budget), int(half_extra))
+    opts = PlanOptions(int(slice_batch), int(memory_budget), int(half_nodes))
     check(lib().matnc_plan_create_ex(c_void_p(net), int_array(flat), len(sliced_ids), int_array(sliced_ids),
                                      len(open_qubits), int_array(open_qubits), len(words), pwords, int(precision),
                                      int(max_rank), ctypes.byref(opts), ctypes.byref(out)))

@@ -487,6 +487,10 @@ static const MfmaCfgH kMfmaCfgsH[] = {
     {7, 5, 3},  // 4: RM=2 RN=1 WM=2 WN=2, TK=8  -> TM=128, TN=32
     {8, 6, 4},  // 5: RM=4 RN=2 WM=2 WN=2, TK=16 -> TM=256, TN=64
     {7, 6, 3},  // 6: RM=2 RN=2 WM=2 WN=2, TK=8  -> TM=128, TN=64
+    // eight waves per workgroup: twice the flops per staged byte of the
+    // four-wave tiles, for the MFMA-bound stem steps (large m, n and k)
+    {8, 7, 4},  // 7: RM=2 RN=4 WM=4 WN=2, TK=16 -> TM=256, TN=128
+    {8, 6, 4},  // 8: RM=2 RN=2 WM=4 WN=2, TK=16 -> TM=256, TN=64
 };
 
 int mfma_h_config_count() { return (int)(sizeof(kMfmaCfgsH) / sizeof(kMfmaCfgsH[0])); }
@@ -516,6 +520,11 @@ static hipError_t launch_mfma_h_cfg(const NodeDesc& d, int cfg, unsigned grid, u
     case 4: hipLaunchKernelGGL((k_mfma_h<2, 1, 2, 2, 8, FAN, HA, HB>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
     case 5: hipLaunchKernelGGL((k_mfma_h<4, 2, 2, 2, 16, FAN, HA, HB>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
     case 6: hipLaunchKernelGGL((k_mfma_h<2, 2, 2, 2, 8, FAN, HA, HB>), dim3(grid), dim3(256), 0, st, d, ws, sig); break;
+    case 7:
+      if (FAN) return hipErrorInvalidValue;  // fan tables hold 32 or 64 columns
+      hipLaunchKernelGGL((k_mfma_h<2, 4, 4, 2, 16, false, HA, HB>), dim3(grid), dim3(512), 0, st, d, ws, sig);
+      break;
+    case 8: hipLaunchKernelGGL((k_mfma_h<2, 2, 4, 2, 16, FAN, HA, HB>), dim3(grid), dim3(512), 0, st, d, ws, sig); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -89,11 +89,15 @@ int guarded(F&& f) {
 
 constexpr uint64_t kAlign = 256;
 
-// complex-half plans: intermediates outside the twig stored in FP16 unless
-// the caller sets matnc_plan_options_t.half_extra -- kDefaultHalfExtra for
-// batches of at least kHalfExtraMinAmps amplitudes, none for smaller ones
-constexpr int kDefaultHalfExtra = 8;
-constexpr int64_t kHalfExtraMinAmps = 4096;
+// Complex-half plans: how many intermediates may be stored in FP16 unless
+// the caller sets matnc_plan_options_t.half_nodes.  With N such tensors the
+// amplitudes carry relative errors of rms e ~ 2.8e-4 sqrt(N); the linear XEB
+// of K amplitudes then moves by about 2 e / sqrt(K) (independent errors,
+// Porter-Thomas amplitudes).  Keeping three times that within the 1e-4 XEB
+// bar gives N <= K / kAmpsPerHalfNode; kMaxHalfNodes keeps e below half of
+// the 3e-3 amplitude bar.
+constexpr int64_t kAmpsPerHalfNode = 282;
+constexpr int kMaxHalfNodes = 28;
 
 // bytes per stored element of node v: complex64 (8) unless the plan is
 // complex-half and v is an FP16-stored branch tensor (4)
@@ -253,16 +257,12 @@ void build_steps(Plan& P) {
   P.cmac_single = P.cmac_multi = P.cmac_inv = P.cmac_total = 0;
   P.bytes_slice = P.bytes_inv = 0;
   const double nsl = std::ldexp(1.0, (int)P.sliced.size());
-  // complex-half storage policy: FP16 with per-instance exponents for
-  //  * the tensors of the twig, whose reuse width is at least a quarter of
-  //    the distinct bitstrings -- each instance feeds only a few amplitudes,
-  //    so their rounding errors stay independent across amplitudes;
-  //  * the P.half_extra other intermediates (stem and narrow branch) whose
-  //    steps carry the most estimated FP32 time: they then run on the FP16
-  //    MFMA kernels and move half the bytes.  Each adds one FP16 rounding
-  //    (relative rms about 2^-11 / sqrt(3)) shared by every amplitude, so
-  //    their number is the precision budget of the plan.
-  // Leaves and the other intermediates stay FP32.
+  // complex-half storage policy: the P.half_nodes intermediates whose steps
+  // carry the most estimated FP32 time are stored in FP16 with per-instance
+  // exponents (they then run on the FP16 MFMA kernels and move half the
+  // bytes); leaves and the other intermediates stay FP32.  Each FP16 tensor
+  // adds one rounding of relative rms about 2^-11 / sqrt(3) = 2.8e-4, so
+  // their number is the precision budget of the plan (see kMaxHalfNodes).
   std::vector<double> t32(P.n_nodes, 0.0);
   for (int v = nt; v < P.n_nodes; ++v) {
     const PNode& V = P.nodes[v];
@@ -285,21 +285,17 @@ void build_steps(Plan& P) {
     const bool gemm = nb + kb >= 8 && mb >= 6 && nb >= 5 && kb >= 3;
     t32[v] = std::max(flops / (gemm ? 100e12 : 40e12), bytes / 3e12) * (V.dep ? nsl : 1.0);
   }
-  std::vector<char> extra(P.n_nodes, 0);
-  if (P.precision == MATNC_CHALF && P.half_extra > 0) {
+  std::vector<char> half(P.n_nodes, 0);
+  if (P.precision == MATNC_CHALF && P.half_nodes > 0) {
     std::vector<int> order;
-    for (int v = nt; v < P.n_nodes; ++v) {
-      const int64_t w = (int64_t)P.nodes[v].keys.size();
-      if (!(w > 1 && 4 * w >= P.n_unique)) order.push_back(v);
-    }
+    for (int v = nt; v < P.n_nodes; ++v) order.push_back(v);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return t32[x] > t32[y]; });
-    for (size_t i = 0; i < order.size() && (int)i < P.half_extra; ++i) extra[order[i]] = 1;
+    for (size_t i = 0; i < order.size() && (int)i < P.half_nodes; ++i) half[order[i]] = 1;
   }
   P.n_half = 0;
   for (int v = 0; v < P.n_nodes; ++v) {
-    const int64_t w = (int64_t)P.nodes[v].keys.size();
-    P.nodes[v].half_store = P.precision == MATNC_CHALF && v >= nt && ((w > 1 && 4 * w >= P.n_unique) || extra[v]);
-    P.n_half += P.nodes[v].half_store ? 1 : 0;
+    P.nodes[v].half_store = half[v] != 0;
+    P.n_half += half[v] ? 1 : 0;
   }
   for (int v = nt; v < P.n_nodes; ++v) {
     PNode& V = P.nodes[v];
@@ -1221,7 +1217,7 @@ int matnc_plan_create(matnc_network net, const int* pairs, int n_sliced, const i
   std::memset(&o, 0, sizeof(o));
   o.slice_batch = slice_batch;
   o.memory_budget = memory_budget;
-  o.half_extra = -1;
+  o.half_nodes = -1;
   return matnc_plan_create_ex(net, pairs, n_sliced, sliced_ids, n_open, open_qubits, k, bitstrings, precision,
                               max_rank, &o, out);
 }
@@ -1233,7 +1229,7 @@ int matnc_plan_create_ex(matnc_network net, const int* pairs, int n_sliced, cons
     if (!opts) fail(MATNC_E_INVALID, "null options");
     const int slice_batch = opts->slice_batch;
     const size_t memory_budget = opts->memory_budget;
-    if (opts->half_extra < -1) fail(MATNC_E_INVALID, "half_extra must be >= -1");
+    if (opts->half_nodes < -1) fail(MATNC_E_INVALID, "half_nodes must be >= -1");
     if (!net || !out) fail(MATNC_E_INVALID, "null argument");
     const Network& N = net->net;
     const int nt = N.n_tensors;
@@ -1256,11 +1252,9 @@ int matnc_plan_create_ex(matnc_network net, const int* pairs, int n_sliced, cons
     P.max_rank_cap = max_rank;
     P.batch = slice_batch;
     P.memory_budget = memory_budget;
-    // the XEB of K amplitudes with relative errors of rms e moves by about
-    // c e / sqrt(K) (c of a few units measured), so smaller batches keep the
-    // stem in FP32
     const int64_t n_amps = k << n_open;
-    P.half_extra = opts->half_extra >= 0 ? opts->half_extra : (n_amps >= kHalfExtraMinAmps ? kDefaultHalfExtra : 0);
+    P.half_nodes = opts->half_nodes >= 0 ? opts->half_nodes
+                                         : (int)std::min<int64_t>(kMaxHalfNodes, n_amps / kAmpsPerHalfNode);
     // tree
     std::vector<char> used(2 * nt - 1, 0);
     for (int j = 0; j < nt - 1; ++j) {

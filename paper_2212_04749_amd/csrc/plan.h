@@ -48,7 +48,7 @@ struct PNode {
   std::vector<int> sl_index;     // the sliced index ids, same order
   // step description (internal nodes)
   bool swap = false;             // true: operand A is child b
-  bool half_store = false;       // complex-half plans: stored as FP16 (twig, and the costliest other steps)
+  bool half_store = false;       // complex-half plans: stored as FP16 (the costliest steps)
   bool rec_max = false;          // complex-half plans: FP32 tensor whose maximum an FP16 consumer needs
   int kernel = 0;                // 0 streaming, 1 MFMA
   int cfg = -1;
@@ -108,8 +108,8 @@ struct Plan {
   int batch = 1;
   int elem_bytes = 8;
   uint64_t memory_budget = 0;    // 0 = no limit
-  int half_extra = 0;            // complex-half: FP16-stored intermediates outside the twig
-  int n_half = 0;                // complex-half: FP16-stored intermediates in all
+  int half_nodes = 0;            // complex-half: budget of FP16-stored intermediates
+  int n_half = 0;                // complex-half: FP16-stored intermediates
   int n_chunks = 1;
   std::vector<Chunk> chunks;
   std::vector<int> chunk_pos;    // node id -> position in chunked (-1 if not there)

@@ -48,5 +48,5 @@ def test_shipped_tuning_file_is_valid():
     for key, cfg in tuned.items():
         m = re.fullmatch(r"(c64|chalf)/(f|h)/(fan/)?(\d+),(\d+),(\d+)/(\d+)", key)
         assert m, key
-        bound = B.matnc_mfma_config_count() if m.group(2) == "f" else 7
+        bound = B.matnc_mfma_config_count() if m.group(2) == "f" else 9
         assert 0 <= cfg < bound, key
