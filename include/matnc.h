@@ -27,8 +27,10 @@
  *
  * Ownership: every host array passed in is copied before the call returns.
  * The library never allocates device memory: all device storage is the
- * caller's workspace (matnc_plan_bind) or the caller's output buffers.  The
- * plan owns host metadata and, while bound, the captured HIP graph.
+ * caller's workspace (matnc_plan_bind) or the caller's output buffers, apart
+ * from one 32 KiB device array per GPU owned by the library for
+ * matnc_contract_noalloc.  The plan owns host metadata and, while bound, the
+ * captured HIP graph.
  *
  * Errors: every call returns MATNC_OK (0) or one of the MATNC_E_* codes and
  * never throws or aborts across the ABI.  matnc_last_error() returns a
@@ -350,6 +352,27 @@ int matnc_contract(const void *A, const void *B, void *C, int64_t batch,
                    const int *posC_m, const int *posC_n,
                    int kernel, void *dev_scratch, size_t scratch_bytes,
                    void *hip_stream);
+
+/*
+ * matnc_contract_noalloc -- matnc_contract for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops): the same
+ * arguments without dev_scratch, the same kernels and results (bit for bit).
+ * The offset tables live in a library-owned device array of 32 KiB per GPU
+ * (one call needs matnc_contract_scratch_bytes() = 24832 bytes of it), held
+ * from the first call on a GPU until the process ends; they are written by a
+ * kernel on hip_stream, so the call neither copies from the host nor waits.
+ * The current device must be the device of hip_stream and of A, B, C.  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (on
+ * different streams, or from different threads) race on it and must be
+ * serialised by the caller.  Nothing is allocated by the call.
+ * Errors: MATNC_E_INVALID (as matnc_contract), MATNC_E_HIP.
+ */
+int matnc_contract_noalloc(const void *A, const void *B, void *C, int64_t batch,
+                           int nm, int nn, int nk,
+                           const int *posA_m, const int *posA_k,
+                           const int *posB_k, const int *posB_n,
+                           const int *posC_m, const int *posC_n,
+                           int kernel, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -66,7 +66,7 @@ EXPORTS = [
     "matnc_execute", "matnc_xeb", "matnc_plan_destroy", "matnc_queue_create",
     "matnc_queue_execute", "matnc_queue_destroy", "matnc_contract_scratch_bytes",
     "matnc_mfma_config_count", "matnc_contract", "matnc_plan_reset_cache", "matnc_plan_profile",
-    "matnc_plan_autotune", "matnc_plan_create_ex", "matnc_queue_workspace_bytes",
+    "matnc_plan_autotune", "matnc_contract_noalloc", "matnc_plan_create_ex", "matnc_queue_workspace_bytes",
     "matnc_queue_bind",
 ]
 
@@ -112,6 +112,9 @@ def lib():
                                        c_int64, POINTER(c_uint64), c_int, c_int, c_void_p, POINTER(c_void_p)]
     L.matnc_queue_workspace_bytes.argtypes = [c_void_p, POINTER(c_size_t)]
     L.matnc_queue_bind.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p]
+    L.matnc_contract_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_int, c_int, c_int,
+                                         POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_int),
+                                         POINTER(c_int), POINTER(c_int), c_int, c_void_p]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("matnc_version", "matnc_last_error", "matnc_contract_scratch_bytes",
@@ -265,6 +268,14 @@ def matnc_contract(A: int, B: int, C: int, batch: int, posA_m, posA_k, posB_k, p
                                len(posA_k), int_array(posA_m), int_array(posA_k), int_array(posB_k),
                                int_array(posB_n), int_array(posC_m), int_array(posC_n), int(kernel),
                                c_void_p(scratch), c_size_t(scratch_bytes), c_void_p(hip_stream)))
+
+
+def matnc_contract_noalloc(A: int, B: int, C: int, batch: int, posA_m, posA_k, posB_k, posB_n, posC_m, posC_n,
+                           kernel: int, hip_stream: int) -> None:
+    check(lib().matnc_contract_noalloc(c_void_p(A), c_void_p(B), c_void_p(C), c_int64(batch), len(posA_m),
+                                       len(posB_n), len(posA_k), int_array(posA_m), int_array(posA_k),
+                                       int_array(posB_k), int_array(posB_n), int_array(posC_m),
+                                       int_array(posC_n), int(kernel), c_void_p(hip_stream)))
 
 
 def matnc_plan_reset_cache(plan: int) -> None:

@@ -25,6 +25,7 @@
 #include <limits>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <stdexcept>
@@ -971,7 +972,7 @@ void write_tune_cache(const char* path, const std::map<std::string, int>& m) {
 }
 
 // ---------------------------------------------------------------------------
-// single pairwise contractions (matnc_contract)
+// single pairwise contractions (matnc_contract, matnc_contract_noalloc)
 
 // scratch of one call: a zero head (int64 sigma slot at byte 0, a zero
 // int32 gather entry at byte 8), then the six offset tables
@@ -1088,6 +1089,46 @@ void launch_contract(const ContractCall& c, const void* A, const void* B, void* 
   const int64_t* sig = reinterpret_cast<const int64_t*>(base);
   hipError_t e = c.kind == 1 ? launch_mfma(d, c.cfg, 0, sig, st) : launch_stream(d, 0, sig, st);
   hip_check(e, "contract launch");
+}
+
+// The scratch of matnc_contract_noalloc: one copy per GPU, held until the
+// process ends, shared by every call on that GPU (calls that overlap on one
+// GPU race on it).  Host code never uses the symbol's name as an address:
+// the device address of each GPU's copy comes from hipGetSymbolAddress,
+// taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[32768];
+
+__global__ void k_contract_tables(TabPos pos, uint32_t* base) {
+  // block t writes table class t; block 0 also clears the head (sigma slot
+  // and the zero gather entry)
+  const int t = blockIdx.x, e = threadIdx.x;
+  if (t == 0 && e < (int)(kAlign / 4)) base[e] = 0u;
+  uint32_t* T = base + kAlign / 4 + t * kTabSize;
+  for (int L = 0; L < kTabLevels; ++L) {
+    uint32_t off = 0;
+    for (int b = 0; b < 8; ++b) {
+      const int bit = 8 * L + b;
+      if (((e >> b) & 1) && bit < pos.nbits[t]) off += 1u << pos.pos[t][bit];
+    }
+    T[L * kTabEntries + e] = off;
+  }
+}
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_dev;  // device address of `scratch` per device id
+
+void* static_scratch_ptr() {
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "get device");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((size_t)dev >= g_scratch_dev.size()) g_scratch_dev.resize((size_t)dev + 1, nullptr);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch symbol address");
+    if (!p) fail(MATNC_E_HIP, "scratch symbol has no device address");
+    g_scratch_dev[dev] = p;
+  }
+  return g_scratch_dev[dev];
 }
 
 // attaches plan P to its static region at dev_workspace (and its arena at
@@ -1740,6 +1781,24 @@ int matnc_contract(const void* A, const void* B, void* C, int64_t batch, int nm,
     hip_check(hipMemcpyAsync(dev_scratch, img.data(), img.size(), hipMemcpyHostToDevice, st), "upload tables");
     hip_check(hipStreamSynchronize(st), "upload tables");
     launch_contract(c, A, B, C, reinterpret_cast<uint64_t>(dev_scratch), st);
+  });
+}
+
+int matnc_contract_noalloc(const void* A, const void* B, void* C, int64_t batch, int nm, int nn, int nk,
+                           const int* posA_m, const int* posA_k, const int* posB_k, const int* posB_n,
+                           const int* posC_m, const int* posC_n, int kernel, void* hip_stream) {
+  return guarded([&] {
+    if (!A || !B || !C) fail(MATNC_E_INVALID, "null argument");
+    const ContractCall c = contract_call(batch, nm, nn, nk, posA_m, posA_k, posB_k, posB_n, posC_m, posC_n, kernel);
+    static_assert(kContractScratchBytes <= sizeof(scratch), "static scratch smaller than one call's tables");
+    const uint64_t base = reinterpret_cast<uint64_t>(static_scratch_ptr());
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    // the same scratch image as matnc_contract uploads, written by a kernel
+    // on the caller's stream: no copy, no wait, nothing allocated
+    hipLaunchKernelGGL(k_contract_tables, dim3(TAB_COUNT), dim3(kTabEntries), 0, st, c.pos,
+                       reinterpret_cast<uint32_t*>(base));
+    hip_check(hipGetLastError(), "table kernel launch");
+    launch_contract(c, A, B, C, base, st);
   });
 }
 
