@@ -250,11 +250,16 @@ def run_leg(api, torch, name, w, net, spec, precision, batch, steps, warmup, arg
 
     err = None
     done = 0
+    check_ms = None
     if check is not None:
         for t, x in enumerate(check["pnet"].tensors):
             run.set_tensor(t, x)
+        ev_c = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev_c[0].record(run.stream)
         step()
+        ev_c[1].record(run.stream)
         run.synchronize()
+        check_ms = ev_c[0].elapsed_time(ev_c[1])
         a = amps.cpu().numpy()
         blocks = (a[..., 0] + 1j * a[..., 1])[np.array(check["groups"])]
         err = errors(blocks, check["ref"], w.n_qubits)
@@ -269,19 +274,33 @@ def run_leg(api, torch, name, w, net, spec, precision, batch, steps, warmup, arg
             run.set_tensor(t, x)
         done = 1
         log(f"{name} {precision}: warm-up pass on the permutation circuit, rel err {err['rel_err']:.2e}")
+    ev_w = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    graph_ms = check_ms
     for i in range(max(0, warmup - done)):
+        ev_w[0].record(run.stream)
         step()
+        ev_w[1].record(run.stream)
         run.synchronize()
-        log(f"{name} {precision}: warm-up {i + done} done")
+        graph_ms = ev_w[0].elapsed_time(ev_w[1])
+        log(f"{name} {precision}: warm-up {i + done} done ({graph_ms:.1f} ms, graph replay)")
+    # the dominant step, from one profiled batch; its launches are then timed
+    # with HIP events inside the timed passes
+    n_batches = -(-run.n_slices // batch)
+    dom = dominant_step(run, precision, n_batches)
     torch.cuda.synchronize()
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    dom_ms, dom_n = 0.0, 0
     evs[0].record(run.stream)
     for i in range(steps):
-        step()
+        run.reset_cache()
+        with torch.cuda.stream(run.stream):
+            amps.zero_()
+        ms, n = run.execute_timed(amps, dom["step"], s_begin, s_end)
+        xeb_out = run.xeb_dev(amps)
         evs[i + 1].record(run.stream)
-        if i >= 1:
-            evs[i].synchronize()
-            log(f"{name} {precision}: timed pass {i - 1} done")
+        dom_ms += ms
+        dom_n += n
+        log(f"{name} {precision}: timed pass {i} queued, step {dom['step']}: {n} launches, {ms / max(n, 1):.3f} ms each")
     torch.cuda.synchronize()
     ms_step = evs[0].elapsed_time(evs[steps]) / steps
     log(f"{name} {precision}: {steps} timed passes, {ms_step:.2f} ms per pass")
@@ -304,8 +323,8 @@ def run_leg(api, torch, name, w, net, spec, precision, batch, steps, warmup, arg
     xeb = float(xeb_out.cpu().item()) if full else None
     if err is None and full:
         err = reference_error(name, amps_c, w.n_qubits)
-    n_batches = -(-run.n_slices // batch)
-    roof, per, t_roof_ms = roofline(run, precision, n_batches, run.n_slices - (n_batches - 1) * batch, name)
+    roof = roofline(dom, dom_ms, dom_n, precision, name)
+    per, t_roof_ms = dom["per"], dom["t_roof_ms"]
     if profile_out:
         write_profile(profile_out, run, spec, net, w, batch, per)
     n_timed = s_end - s_begin
@@ -321,6 +340,10 @@ def run_leg(api, torch, name, w, net, spec, precision, batch, steps, warmup, arg
         "steps": steps,
         "warmup": warmup,
         "ms_per_step": ms_step,
+        # a warm-up pass replayed from the captured graphs (the timed passes
+        # launch the same kernels one by one, with events around the
+        # dominant step's launches)
+        "ms_per_step_graph": graph_ms,
         "value": info.n_amplitudes / secs,
         "unit": "amplitudes/s",
         "complex_tflops": tflops,
@@ -440,19 +463,16 @@ def cpu_baseline_tn(w, cap: int = 25, seed: int = 2025, min_s: float = 10.0, max
                       f"scaled by {n_sl} slices x {len(words)} groups to {job_s:.3g} s for the whole job"}
 
 
-def roofline(run, precision, n_batches, nb_last, workload):
-    """Roofline of the dominant launch of a profiled pass.  Every contraction
-    step is one launch of one kernel configuration on one shape; the
-    dominant one is the step with the largest share of the pass
-    (slice-dependent steps run once per slice batch).  Its bound is the
-    larger of its algorithmic flops over the MFMA peak of its kernel and its
-    algorithmic bytes over the HBM peak, and achieved is that quantity per
-    launch over the launch's time.  Also returns per-kernel-id aggregates
-    and the pass's summed per-step roofline time (ms)."""
+def dominant_step(run, precision, n_batches):
+    """The step with the largest share of a pass, from one profiled batch
+    (slice-dependent steps run once per slice batch).  Also returns per-
+    kernel-id aggregates and the pass's summed per-step roofline time (ms):
+    for every step the larger of its algorithmic flops over the MFMA peak of
+    its kernel and its algorithmic bytes over the HBM peak."""
     prof = run.profile(0, min(run.slice_batch, run.n_slices))
     per = {}
     steps = []
-    t_roof = 0.0  # sum over steps of max(flops / MFMA peak, bytes / HBM peak), ms
+    t_roof = 0.0
     for j, ((ms, kid, cmac, by), dep) in enumerate(zip(prof, run.step_dep())):
         if ms < 0:
             continue
@@ -470,8 +490,19 @@ def roofline(run, precision, n_batches, nb_last, workload):
         steps.append((ms * reps, j, ms, kid, cmac, by, reps, tf, tb, peak))
     total = sum(x[0] for x in steps)
     share, j, ms, kid, cmac, by, reps, tf, tb, peak = max(steps)
+    return {"step": j, "profile_ms": ms, "kid": kid, "cmac": cmac, "bytes": by, "tf": tf, "tb": tb, "peak": peak,
+            "share": share / total, "per": per, "t_roof_ms": t_roof}
+
+
+def roofline(dom, ms_total, launches, precision, workload):
+    """Roofline of the dominant step's kernel: its bound is the larger of its
+    algorithmic flops over the MFMA peak of the kernel and its algorithmic
+    bytes over the HBM peak; achieved is that quantity per launch over the
+    mean launch time measured with HIP events in the timed passes."""
+    j, kid, cmac, by, peak = dom["step"], dom["kid"], dom["cmac"], dom["bytes"], dom["peak"]
+    ms = ms_total / max(launches, 1)
     t = ms / 1e3
-    if kid >= 100 and tf >= tb:
+    if kid >= 100 and dom["tf"] >= dom["tb"]:
         r = {"bound": "mfma", "achieved": 8 * cmac / t / 1e12, "peak": peak, "unit": "TFLOP/s"}
     else:
         r = {"bound": "hbm", "achieved": by / t / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
@@ -484,10 +515,12 @@ def roofline(run, precision, n_batches, nb_last, workload):
                    f"cfg {kid % 100}") + f", step {j}"
     r["kernel_id"] = kid
     r["step"] = j
-    r["launches"] = reps
+    r["launches"] = launches
     r["mean_launch_ms"] = ms
-    r["share_of_step"] = share / total
-    return r, per, t_roof
+    r["timing"] = "HIP events on the plan's stream around each launch of the step in the timed passes"
+    r["profile_pass_ms"] = dom["profile_ms"]
+    r["share_of_step"] = dom["share"]
+    return r
 
 
 def pmc_traffic(workload: str, precision: str, kernel_id: int, step: int):

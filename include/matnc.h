@@ -228,6 +228,22 @@ int matnc_plan_bind(matnc_plan plan, void *dev_workspace, size_t bytes, void *hi
  */
 int matnc_execute(matnc_plan plan, int64_t slice_begin, int64_t slice_end, double *amps_dev);
 
+/* matnc_execute_timed: the same work as matnc_execute over the same range
+ * (same launches, same results, bit for bit), launched one by one rather
+ * than replayed from captured graphs, with a pair of HIP events on the
+ * bound stream around every launch of contraction step `step` (0 ..
+ * n_tensors - 2, the order of the plan's pairs).  It blocks until the
+ * stream is idle, then stores in *ms_total the summed event time of those
+ * launches (milliseconds) and in *launches their number (once per slice
+ * batch and key chunk for a slice-dependent step, once for an invariant
+ * one computed by this call, 0 for an invariant one already cached).  For
+ * timing one kernel inside a throughput measurement; the events are the
+ * library's own and freed before it returns.
+ * Errors: as matnc_execute, MATNC_E_INVALID (step, null outputs).
+ */
+int matnc_execute_timed(matnc_plan plan, int64_t slice_begin, int64_t slice_end, double *amps_dev, int step,
+                        double *ms_total, int64_t *launches);
+
 /*
  * matnc_xeb -- linear XEB of the amplitudes in amps_dev over all
  * k * 2^n_open entries: F = (2^n_qubits / K) sum |a|^2 - 1, a deterministic

@@ -137,6 +137,17 @@ class Contraction:
         B.matnc_execute(self._plan, begin, end, amps.data_ptr())
         return amps
 
+    def execute_timed(self, amps, step: int, begin: int = 0, end: Optional[int] = None):
+        """execute() launched one by one with HIP events around every launch
+        of contraction step `step`; waits for the pass and returns (summed
+        milliseconds of those launches, their number)."""
+        self._check_amps(amps)
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        amps.record_stream(self.stream)
+        if end is None:
+            end = self.n_slices
+        return B.matnc_execute_timed(self._plan, begin, end, amps.data_ptr(), step)
+
     def xeb_dev(self, amps):
         self._check_amps(amps)
         with self.torch.cuda.stream(self.stream):

@@ -67,7 +67,7 @@ EXPORTS = [
     "matnc_queue_execute", "matnc_queue_destroy", "matnc_contract_scratch_bytes",
     "matnc_mfma_config_count", "matnc_contract", "matnc_plan_reset_cache", "matnc_plan_profile",
     "matnc_plan_autotune", "matnc_contract_noalloc", "matnc_plan_create_ex", "matnc_queue_workspace_bytes",
-    "matnc_queue_bind",
+    "matnc_queue_bind", "matnc_execute_timed",
 ]
 
 
@@ -92,6 +92,8 @@ def lib():
     L.matnc_plan_set_tensor.argtypes = [c_void_p, c_int, POINTER(c_double)]
     L.matnc_plan_bind.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p]
     L.matnc_execute.argtypes = [c_void_p, c_int64, c_int64, c_void_p]
+    L.matnc_execute_timed.argtypes = [c_void_p, c_int64, c_int64, c_void_p, c_int, POINTER(c_double),
+                                      POINTER(ctypes.c_int64)]
     L.matnc_xeb.argtypes = [c_void_p, c_void_p, c_void_p]
     L.matnc_plan_destroy.argtypes = [c_void_p]
     L.matnc_queue_create.argtypes = [c_int, POINTER(c_void_p), POINTER(c_void_p)]
@@ -218,6 +220,15 @@ def matnc_plan_bind(plan: int, dev_workspace: int, nbytes: int, hip_stream: int)
 
 def matnc_execute(plan: int, slice_begin: int, slice_end: int, amps_dev: int) -> None:
     check(lib().matnc_execute(c_void_p(plan), c_int64(slice_begin), c_int64(slice_end), c_void_p(amps_dev)))
+
+
+def matnc_execute_timed(plan: int, slice_begin: int, slice_end: int, amps_dev: int, step: int):
+    """(summed event ms, number of launches) of step's launches in the pass."""
+    ms = c_double(0.0)
+    n = ctypes.c_int64(0)
+    check(lib().matnc_execute_timed(c_void_p(plan), c_int64(slice_begin), c_int64(slice_end), c_void_p(amps_dev),
+                                    int(step), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def matnc_xeb(plan: int, amps_dev: int, xeb_dev: int) -> None:

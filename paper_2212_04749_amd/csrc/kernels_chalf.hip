@@ -244,29 +244,35 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
     // raw operand words in flight (an FP32 element, or a half2 in .x); the
     // FP32 -> FP16 conversion happens when the tile is written to LDS, after
     // the MFMA work of the current step, so the loads are not waited for
-    // inside the load phase
-    typename AStage<HA>::type ra[EQA][4];
-    typename AStage<HB>::type rb[EQB][4];
-    auto gload = [&](uint32_t kba, uint32_t kbb) {
+    // inside the load phase.  S register stages: with two, the loads of k
+    // step k + 2 are issued before the MFMA work of step k, so that two
+    // steps of MFMA work cover their latency.  Two only for the 8-wave tiles
+    // whose second stage still fits two waves per SIMD (FP16 operands); the
+    // 4-wave tiles would lose half their occupancy to it.
+    constexpr int SW = EQA * 4 * (HA ? 1 : 2) + EQB * 4 * (HB ? 1 : 2);  // words per stage
+    constexpr int S = (NT == 512 && SW <= 12) ? 2 : 1;
+    typename AStage<HA>::type ra[S][EQA][4];
+    typename AStage<HB>::type rb[S][EQB][4];
+    auto gload = [&](int st, uint32_t kba, uint32_t kbb) {
 #pragma unroll
       for (int e = 0; e < EQA; ++e)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) ra[e][q] = AStage<HA>::load(pa, aoff[e][q] + kba);
+        for (int q = 0; q < 4; ++q) ra[st][e][q] = AStage<HA>::load(pa, aoff[e][q] + kba);
       if (bstage) {
 #pragma unroll
         for (int e = 0; e < EQB; ++e)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) rb[e][q] = AStage<HB>::load(pbe[e], boff[e][q] + kbb);
+          for (int q = 0; q < 4; ++q) rb[st][e][q] = AStage<HB>::load(pbe[e], boff[e][q] + kbb);
       }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf, int st) {
 #pragma unroll
       for (int e = 0; e < EQA; ++e) {
         uint4 v;
-        v.x = AStage<HA>::bits(ra[e][0], ca);
-        v.y = AStage<HA>::bits(ra[e][1], ca);
-        v.z = AStage<HA>::bits(ra[e][2], ca);
-        v.w = AStage<HA>::bits(ra[e][3], ca);
+        v.x = AStage<HA>::bits(ra[st][e][0], ca);
+        v.y = AStage<HA>::bits(ra[st][e][1], ca);
+        v.z = AStage<HA>::bits(ra[st][e][2], ca);
+        v.w = AStage<HA>::bits(ra[st][e][3], ca);
         *reinterpret_cast<uint4*>(&As[buf][akq[e] * AQ + 4 * amm[e]]) = v;
       }
       if (bstage) {
@@ -275,7 +281,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
           uint32_t lo[4], hi[4];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const uint32_t h = AStage<HB>::bits(rb[e][q], cbe[e]);
+            const uint32_t h = AStage<HB>::bits(rb[st][e][q], cbe[e]);
             const uint32_t re = h & 0xffffu, im = h >> 16;
             lo[q] = re | ((im ^ 0x8000u) << 16);  // (Br, -Bi)
             hi[q] = im | (re << 16);              // (Bi, Br)
@@ -294,30 +300,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
       for (int q = 0; q < RN; ++q)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][q][r] = 0.f;
-
-    // output offsets of this lane's m values, fetched before the k loop
-    uint32_t om[RM];
-#pragma unroll
-    for (int i = 0; i < RM; ++i) om[i] = tlook(tab + TAB_CM * kTabSize, m0 + (wm * RM + i) * 32 + l32);
-
-    // k offsets one step ahead of the loads that use them
-    uint32_t kba = tlook(ctab + TAB_AK * kTabSize, 0u), kbb = tlook(ctab + TAB_BK * kTabSize, 0u);
-    gload(kba, kbb);
-    if (ksteps > 1) {
-      kba = tlook(ctab + TAB_AK * kTabSize, (uint32_t)TK);
-      kbb = tlook(ctab + TAB_BK * kTabSize, (uint32_t)TK);
-    }
-    lstore(0);
-    __syncthreads();
-    for (int ks = 0; ks < ksteps; ++ks) {
-      const int buf = ks & 1;
-      if (ks + 1 < ksteps) {
-        gload(kba, kbb);
-        if (ks + 2 < ksteps) {
-          kba = tlook(ctab + TAB_AK * kTabSize, (uint32_t)(ks + 2) * TK);
-          kbb = tlook(ctab + TAB_BK * kTabSize, (uint32_t)(ks + 2) * TK);
-        }
-      }
+    // the MFMA work of one k step from LDS buffer buf
+    auto kstep = [&](int buf) {
 #pragma unroll
       for (int g = 0; g < TK / 8; ++g) {
         const int kq = 2 * g + half;  // this lane's quad of complex k
@@ -338,8 +322,47 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
           for (int q = 0; q < RN; ++q)
             acc[i][q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xv[q], yv[i], acc[i][q], 0, 0, 0);
       }
-      if (ks + 1 < ksteps) lstore(buf ^ 1);
-      __syncthreads();
+    };
+
+    // output offsets of this lane's m values, fetched before the k loop
+    uint32_t om[RM];
+#pragma unroll
+    for (int i = 0; i < RM; ++i) om[i] = tlook(tab + TAB_CM * kTabSize, m0 + (wm * RM + i) * 32 + l32);
+
+    // stages 0 .. S-1 hold k steps 0 .. S-1; kna, knb: k offsets of the next
+    // step to load (S), fetched one load ahead of their use
+    gload(0, tlook(ctab + TAB_AK * kTabSize, 0u), tlook(ctab + TAB_BK * kTabSize, 0u));
+#pragma unroll
+    for (int u = 1; u < S; ++u)
+      if (u < ksteps)
+        gload(u, tlook(ctab + TAB_AK * kTabSize, (uint32_t)(u * TK)),
+              tlook(ctab + TAB_BK * kTabSize, (uint32_t)(u * TK)));
+    uint32_t kna = 0, knb = 0;
+    if (S < ksteps) {
+      kna = tlook(ctab + TAB_AK * kTabSize, (uint32_t)(S * TK));
+      knb = tlook(ctab + TAB_BK * kTabSize, (uint32_t)(S * TK));
+    }
+    lstore(0, 0);
+    __syncthreads();
+    for (int ks = 0; ks < ksteps; ks += S) {
+#pragma unroll
+      for (int u = 0; u < S; ++u) {
+        const int k = ks + u;
+        if (k < ksteps) {
+          // stage u held step k and was written to LDS at the end of step
+          // k - 1: it now takes step k + S
+          if (k + S < ksteps) {
+            gload(u, kna, knb);
+            if (k + S + 1 < ksteps) {
+              kna = tlook(ctab + TAB_AK * kTabSize, (uint32_t)(k + S + 1) * TK);
+              knb = tlook(ctab + TAB_BK * kTabSize, (uint32_t)(k + S + 1) * TK);
+            }
+          }
+          kstep(k & 1);
+          if (k + 1 < ksteps) lstore((k + 1) & 1, (u + 1) % S);
+          __syncthreads();
+        }
+      }
     }
 
     // output scale of this instance

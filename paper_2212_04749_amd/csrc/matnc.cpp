@@ -845,12 +845,37 @@ void launch_node(const Plan& P, const PNode& V, const NodeDesc& d, hipStream_t s
 
 // one slice batch of chunk c: the per-batch nodes, then the slice-sum of
 // the chunk's rows into amps (skipped when amps is null)
-void launch_batch(const Plan& P, int c, int nb, hipStream_t st, double* amps) {
+// HIP events around every launch of one node (the rest run as usual)
+struct StepTimer {
+  int v = -1;
+  std::vector<hipEvent_t> ev;  // (begin, end) pairs, one per launch
+  ~StepTimer() {
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+void launch_node_timed(const Plan& P, int v, const NodeDesc& d, hipStream_t st, StepTimer* t) {
+  if (!t || v != t->v) {
+    launch_node(P, P.nodes[v], d, st);
+    return;
+  }
+  for (int i = 0; i < 2; ++i) {
+    t->ev.push_back(nullptr);
+    hip_check(hipEventCreate(&t->ev.back()), "event create");
+  }
+  const size_t n = t->ev.size();
+  hip_check(hipEventRecord(t->ev[n - 2], st), "event record");
+  launch_node(P, P.nodes[v], d, st);
+  hip_check(hipEventRecord(t->ev[n - 1], st), "event record");
+}
+
+void launch_batch(const Plan& P, int c, int nb, hipStream_t st, double* amps, StepTimer* t = nullptr) {
   const int64_t* sig = reinterpret_cast<const int64_t*>(P.ws + P.sigma_off);
   const int ob = (int)P.open_qubits.size();
   if (P.precision == MATNC_CHALF)
     hip_check(launch_zero(P.ws + P.dep_scale_lo, P.dep_scale_hi - P.dep_scale_lo, st), "clear scales");
-  for (int v : P.loop) launch_node(P, P.nodes[v], node_desc(P, v, nb, c), st);
+  for (int v : P.loop) launch_node_timed(P, v, node_desc(P, v, nb, c), st, t);
   if (!amps) return;
   const Chunk& C = P.chunks[c];
   const OpDesc root = root_desc(P, c);
@@ -861,18 +886,18 @@ void launch_batch(const Plan& P, int c, int nb, hipStream_t st, double* amps) {
   hip_check(er, "slice sum");
 }
 
-void launch_prologue(const Plan& P, hipStream_t st) {
+void launch_prologue(const Plan& P, hipStream_t st, StepTimer* t = nullptr) {
   if (P.precision == MATNC_CHALF)
     hip_check(launch_zero(P.ws + P.inv_scale_lo, P.inv_scale_hi - P.inv_scale_lo, st), "clear scales");
-  for (int v : P.prologue) launch_node(P, P.nodes[v], node_desc(P, v, 1), st);
+  for (int v : P.prologue) launch_node_timed(P, v, node_desc(P, v, 1), st, t);
 }
 
 // chunk c's instances of the per-chunk invariant nodes
-void launch_chunk_prologue(const Plan& P, int c, hipStream_t st) {
+void launch_chunk_prologue(const Plan& P, int c, hipStream_t st, StepTimer* t = nullptr) {
   if (P.cpro.empty()) return;
   if (P.precision == MATNC_CHALF)
     hip_check(launch_zero(P.ws + P.cpro_scale_lo, P.cpro_scale_hi - P.cpro_scale_lo, st), "clear scales");
-  for (int v : P.cpro) launch_node(P, P.nodes[v], node_desc(P, v, 1, c), st);
+  for (int v : P.cpro) launch_node_timed(P, v, node_desc(P, v, 1, c), st, t);
 }
 
 void release_graph(Plan& P) {
@@ -1439,6 +1464,49 @@ int matnc_execute(matnc_plan plan, int64_t slice_begin, int64_t slice_end, doubl
           launch_batch(P, c, nb, st, amps_dev);
       }
     }
+  });
+}
+
+int matnc_execute_timed(matnc_plan plan, int64_t slice_begin, int64_t slice_end, double* amps_dev, int step,
+                        double* ms_total, int64_t* launches) {
+  return guarded([&] {
+    if (!plan || !ms_total || !launches) fail(MATNC_E_INVALID, "null argument");
+    Plan& P = plan->p;
+    if (!P.bound) fail(MATNC_E_STATE, "execute before bind");
+    if (!amps_dev) fail(MATNC_E_INVALID, "null amplitude buffer");
+    const int64_t ns = (int64_t)1 << P.sliced.size();
+    if (slice_begin < 0 || slice_end < slice_begin || slice_end > ns) fail(MATNC_E_INVALID, "bad slice range");
+    const int nt = P.net.n_tensors;
+    if (step < 0 || step > nt - 2) fail(MATNC_E_INVALID, "step out of range");
+    StepTimer T;
+    T.v = nt + step;
+    hipStream_t st = P.stream;
+    int64_t* sig = reinterpret_cast<int64_t*>(P.ws + P.sigma_off);
+    claim_arena(P);
+    if (!P.inv_valid) {
+      hip_check(launch_set_i64(sig, 0, st), "set sigma");
+      launch_prologue(P, st, &T);
+      P.inv_valid = true;
+    }
+    if (slice_end > slice_begin) {
+      for (int c = 0; c < P.n_chunks; ++c) {
+        launch_chunk_prologue(P, c, st, &T);
+        for (int64_t s0 = slice_begin; s0 < slice_end; s0 += P.batch) {
+          const int nb = (int)std::min<int64_t>(P.batch, slice_end - s0);
+          hip_check(launch_set_i64(sig, s0, st), "set sigma");
+          launch_batch(P, c, nb, st, amps_dev, &T);
+        }
+      }
+    }
+    hip_check(hipStreamSynchronize(st), "timed execute sync");
+    double total = 0.0;
+    for (size_t i = 0; i + 1 < T.ev.size(); i += 2) {
+      float ms = 0.f;
+      hip_check(hipEventElapsedTime(&ms, T.ev[i], T.ev[i + 1]), "event time");
+      total += ms;
+    }
+    *ms_total = total;
+    *launches = (int64_t)(T.ev.size() / 2);
   });
 }
 

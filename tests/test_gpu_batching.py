@@ -53,6 +53,44 @@ def test_graph_replays_match_eager(precision):
     e_run.close()
 
 
+@pytest.mark.parametrize("precision", ["c64", "chalf"])
+def test_timed_execute_matches_graph_pass(precision):
+    # the event-timed pass launches the same kernels one by one: bit-identical
+    # amplitudes to the graph replay; a slice-dependent step is timed once per
+    # slice batch, an invariant one once on a cold stem cache and never after
+    torch = require_gpu()
+    circ = random_circuit(GridSpec(3, 4), 8, 5)
+    words = uniform_bitstrings(12, 64, 6)
+    say(f"timed execute {precision}")
+    run, _ = build(circ, words, 7, 4, precision)
+    ref = run.execute()
+    run.synchronize()
+    ref = ref.cpu().numpy()
+    dep = run.step_dep()
+    prof = run.profile()
+    n_batches = -(-run.n_slices // run.slice_batch)
+    j_dep = max((j for j in range(len(dep)) if dep[j]), key=lambda j: prof[j][0])
+    j_inv = next((j for j in range(len(dep)) if not dep[j] and prof[j][0] >= 0), None)
+    for j in [j_dep] + ([j_inv] if j_inv is not None else []):
+        run.reset_cache()
+        amps = run.new_amplitudes()
+        ms, n = run.execute_timed(amps, j)
+        assert np.array_equal(amps.cpu().numpy(), ref), f"step {j}"
+        if dep[j]:
+            assert n == n_batches * run.info.n_chunks, (j, n)
+        else:
+            assert n in (1, run.info.n_chunks), (j, n)
+        assert ms > 0.0
+        # warm stem cache: a cached invariant step is not launched again (one
+        # wider than a key chunk is, once per chunk)
+        amps.zero_()
+        ms2, n2 = run.execute_timed(amps, j)
+        assert np.array_equal(amps.cpu().numpy(), ref)
+        assert n2 == n if dep[j] else n2 in (0, run.info.n_chunks)
+    say(f"timed steps {j_dep} (slice-dependent), {j_inv} (invariant)")
+    run.close()
+
+
 def test_autotune_keeps_parity_and_writes_cache(tmp_path):
     require_gpu()
     from paper_2212_04749_amd import binding as B

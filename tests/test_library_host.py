@@ -102,6 +102,9 @@ def test_error_paths():
         B.matnc_execute(p, 0, 1, 0x1000)
     assert e.value.code == B.MATNC_E_STATE
     assert "bind" in B.matnc_last_error()
+    with pytest.raises(B.MatncError) as e:
+        B.matnc_execute_timed(p, 0, 1, 0x1000, 0)
+    assert e.value.code == B.MATNC_E_STATE
     # set_tensor: tensor id out of range; a valid id on an unbound plan only
     # replaces the host copy (uploaded at bind)
     with pytest.raises(B.MatncError) as e:
