@@ -61,7 +61,11 @@ struct NodeDesc {
   uint64_t fan_off;
   int64_t n_fan;         // rows of the fan table (per slice)
   int32_t fan_tn;
-  int32_t pad1;
+  // tile order: units (output instances, or fan-table rows) in blocks of
+  // fan_rows with the units innermost (see unit_tile); 1 (plain) or 2 (fan
+  // tables), or about the number of units that share one A instance when
+  // that instance is too large for the caches
+  int32_t fan_rows;
 };
 
 // Scaling of one stored instance in complex-half plans: true value = stored

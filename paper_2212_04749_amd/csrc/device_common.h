@@ -82,29 +82,25 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t vid, int64_t total) {
   return x * q + (x < r ? x : r) + k;
 }
 
-// Logical (unit, tile) of a logical tile index.  Plain steps: tiles of one
-// unit innermost.  Fan-out steps: the rows of the fan table that read one A
-// instance are adjacent (the table is grouped by A instance), and most groups
-// span two rows; pairing consecutive rows with the m tile outermost inside
-// the pair makes the two tiles that read the same A tile adjacent, so they
-// run together on one XCD and the second read hits its L2.  A bijection on
-// [0, units * tiles) (an odd last row keeps its own order).
-template <bool FAN>
-__device__ __forceinline__ void unit_tile(int64_t lt, int64_t units, int64_t tiles, int64_t& u, int64_t& t) {
-  if (!FAN) {
-    u = lt / tiles;
-    t = lt - u * tiles;
-    return;
-  }
-  const int64_t pair = lt / (2 * tiles);
-  const int64_t r = lt - pair * 2 * tiles;
-  if (2 * pair + 1 >= units) {
-    u = 2 * pair;
-    t = r;
-  } else {
-    u = 2 * pair + (r & 1);
-    t = r >> 1;
-  }
+// Logical (unit, tile) of a logical tile index.  Units (output instances,
+// or fan-table rows) are taken in blocks of R; inside a block the tile
+// index is outermost, so that the R tiles at one position of the R units
+// run next to each other on one XCD.  Units that read the same A instance
+// are adjacent (fan tables are grouped by A instance, plain instances are
+// in key order), so the later reads of each A tile hit the L2.  R = 1
+// (plain steps) is the unit-major order; fan-out steps, whose A instances
+// are shared by about two rows, take R = 2; a unit group sharing an A
+// instance far larger than the caches takes R = its size, so that the
+// instance streams from HBM once while the group's B instances are re-read
+// from the caches.  A bijection on [0, units * tiles) for any R >= 1 (a
+// short last block keeps the same order over its units).
+__device__ __forceinline__ void unit_tile(int64_t lt, int64_t units, int64_t tiles, int64_t R, int64_t& u,
+                                          int64_t& t) {
+  const int64_t blk = lt / (R * tiles);
+  const int64_t r = lt - blk * R * tiles;
+  const int64_t rows = units - blk * R < R ? units - blk * R : R;  // units in this block
+  u = blk * R + r % rows;
+  t = r / rows;
 }
 
 template <typename P>

@@ -127,11 +127,11 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
 
   for (int64_t blk = blockIdx.x; blk < units * tiles; blk += gridDim.x) {
     // logical tile order: n tiles innermost (they share the A tile), then m
-    // tiles, then instances / fan rows (fan rows in pairs, see unit_tile);
+    // tiles, then instances / fan rows (fan rows in blocks, see unit_tile);
     // each XCD takes a contiguous range
     const int64_t lt = xcd_tile(blk, units * tiles);
     int64_t u, t;
-    unit_tile<FAN>(lt, units, tiles, u, t);
+    unit_tile(lt, units, tiles, d.fan_rows > 0 ? (int64_t)d.fan_rows : (FAN ? 2 : 1), u, t);
     const uint32_t m0 = (uint32_t)((t / nt_count) * TM);
     const uint32_t n0 = (uint32_t)((t % nt_count) * TN);
     int64_t s, j;

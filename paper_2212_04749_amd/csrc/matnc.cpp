@@ -252,6 +252,39 @@ void make_fan(const std::vector<int32_t>& ga, int slots, std::vector<int32_t>& o
   }
 }
 
+// tile-order block (NodeDesc::fan_rows) of units whose A instances are
+// a_of(0 .. n-1) (adjacent units with equal values share one): when the A
+// instance is too large for the caches to keep it between blocks of `dflt`
+// units (64 MiB), the median number of units per A instance if that is 4 or
+// more (a block then reads about one or two A instances per tile), else dflt
+template <typename F>
+int32_t block_units(size_t n, F a_of, uint64_t a_inst_bytes, int32_t dflt) {
+  if (n == 0 || a_inst_bytes < (64ull << 20)) return dflt;
+  std::vector<int64_t> runs;
+  int64_t run = 0;
+  for (size_t r = 0; r < n; ++r) {
+    ++run;
+    if (r + 1 == n || a_of(r + 1) != a_of(r)) {
+      runs.push_back(run);
+      run = 0;
+    }
+  }
+  std::nth_element(runs.begin(), runs.begin() + runs.size() / 2, runs.end());
+  const int64_t g = runs[runs.size() / 2];
+  return g >= 4 ? (int32_t)g : dflt;
+}
+
+// ... of a fan table (rows of `slots` output instances)
+int32_t fan_block_rows(const std::vector<int32_t>& fanv, int slots, const std::vector<int32_t>& ga,
+                       uint64_t a_inst_bytes) {
+  return block_units(fanv.size() / (size_t)slots, [&](size_t r) { return ga[fanv[r * slots]]; }, a_inst_bytes, 2);
+}
+
+// ... of the instances of a plain step
+int32_t plain_block_units(const std::vector<int32_t>& ga, uint64_t a_inst_bytes) {
+  return block_units(ga.size(), [&](size_t j) { return ga[j]; }, a_inst_bytes, 1);
+}
+
 void build_steps(Plan& P) {
   const int nt = P.net.n_tensors;
   P.n_mfma = 0;
@@ -380,12 +413,16 @@ void build_steps(Plan& P) {
             // both tile widths' tables, so that the tuner may pick either
             make_fan(V.ga, 32 >> nb, V.fanv[0], V.n_fan[0]);
             make_fan(V.ga, 64 >> nb, V.fanv[1], V.n_fan[1]);
+            const uint64_t ab = (1ull << A.idx.size()) * eb_of(P, V.swap ? V.b : V.a);
+            V.fan_rows[0] = fan_block_rows(V.fanv[0], 32 >> nb, V.ga, ab);
+            V.fan_rows[1] = fan_block_rows(V.fanv[1], 64 >> nb, V.ga, ab);
             break;
           }
         }
       }
     }
     if (V.kernel == 1) ++P.n_mfma;
+    V.unit_rows = plain_block_units(V.ga, (1ull << A.idx.size()) * eb_of(P, V.swap ? V.b : V.a));
     V.rec_max = false;
     const double cm = std::ldexp(1.0, mb + nb + kb);
     const double w = (double)V.keys.size();
@@ -489,9 +526,14 @@ void build_chunks(Plan& P, int n_chunks) {
         N.ga.push_back(pa >= 0 ? find(local[pa], ua) : find(P.nodes[ca].keys, ua));
         N.gb.push_back(pb >= 0 ? find(local[pb], ub) : find(P.nodes[cb].keys, ub));
       }
+      N.unit_rows = plain_block_units(N.ga, (1ull << P.nodes[ca].idx.size()) * eb_of(P, ca));
       if (V.fan) {
-        make_fan(N.ga, 32 >> (int)V.N.size(), N.fanv[0], N.n_fan[0]);
-        make_fan(N.ga, 64 >> (int)V.N.size(), N.fanv[1], N.n_fan[1]);
+        const int nbits = (int)V.N.size();
+        make_fan(N.ga, 32 >> nbits, N.fanv[0], N.n_fan[0]);
+        make_fan(N.ga, 64 >> nbits, N.fanv[1], N.n_fan[1]);
+        const uint64_t ab = (1ull << P.nodes[ca].idx.size()) * eb_of(P, ca);
+        N.fan_rows[0] = fan_block_rows(N.fanv[0], 32 >> nbits, N.ga, ab);
+        N.fan_rows[1] = fan_block_rows(N.fanv[1], 64 >> nbits, N.ga, ab);
       }
     }
     // rows of the batch whose root key falls in this chunk
@@ -797,6 +839,9 @@ NodeDesc node_desc(const Plan& P, int v, int nb, int c = 0) {
     d.fan_off = pos >= 0 ? P.chunks[c].nodes[pos].fan_off[t] : V.fan_off[t];
     d.n_fan = pos >= 0 ? P.chunks[c].nodes[pos].n_fan[t] : V.n_fan[t];
     d.fan_tn = V.fan_tn;
+    d.fan_rows = pos >= 0 ? P.chunks[c].nodes[pos].fan_rows[t] : V.fan_rows[t];
+  } else {
+    d.fan_rows = pos >= 0 ? P.chunks[c].nodes[pos].unit_rows : V.unit_rows;
   }
   return d;
 }

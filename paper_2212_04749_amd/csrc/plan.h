@@ -57,6 +57,8 @@ struct PNode {
   std::vector<int32_t> fanv[2];  // fan tables for 32- and 64-column tiles (unchunked plans)
   int64_t n_fan[2] = {0, 0};
   uint64_t fan_off[2] = {0, 0};
+  int32_t fan_rows[2] = {2, 2};  // tile-order blocks of the two tables (NodeDesc::fan_rows)
+  int32_t unit_rows = 1;         // ... of the output instances of a plain MFMA step
   std::vector<int> M, N, K;      // virtual orders of the three index classes
   // memory
   uint64_t inst_elems = 0;
@@ -79,6 +81,8 @@ struct ChunkNode {
   std::vector<int32_t> fanv[2];       // fan tables over this chunk's instances (32, 64 columns)
   int64_t n_fan[2] = {0, 0};
   uint64_t fan_off[2] = {0, 0};
+  int32_t fan_rows[2] = {2, 2};
+  int32_t unit_rows = 1;
 };
 
 struct Chunk {
