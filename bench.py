@@ -743,7 +743,8 @@ def main():
         "dtype": head["dtype"],
         "data": "synthetic",
     }
-    out |= {k: head[k] for k in ("complex_tflops", "mfma_peak_frac", "step_roofline_ms", "step_roofline_frac",
+    out |= {k: head[k] for k in ("ms_per_step_graph", "complex_tflops", "mfma_peak_frac", "step_roofline_ms",
+                                 "step_roofline_frac",
                                  "xeb", "error_vs_fp64", "bind_s", "autotune_s")}
     out["plan_s"] = t_plan
     out["config"] = head["config"]
