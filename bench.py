@@ -304,6 +304,7 @@ def run_leg(api, torch, name, w, net, spec, precision, batch, steps, warmup, arg
         log(f"{name} {precision}: timed pass {i} queued, step {dom['step']}: {n} launches, {ms / max(n, 1):.3f} ms each")
     torch.cuda.synchronize()
     ms_step = evs[0].elapsed_time(evs[steps]) / steps
+    ms_passes = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
     log(f"{name} {precision}: {steps} timed passes, {ms_step:.2f} ms per pass")
     full = (s_begin, s_end) == (0, run.n_slices)
     ms_slices = None
@@ -345,6 +346,9 @@ def run_leg(api, torch, name, w, net, spec, precision, batch, steps, warmup, arg
         # launch the same kernels one by one, with events around the
         # dominant step's launches)
         "ms_per_step_graph": graph_ms,
+        # each timed pass (the mean of these is ms_per_step)
+        "ms_per_pass": ms_passes,
+        "ms_per_pass_median": sorted(ms_passes)[len(ms_passes) // 2],
         "value": info.n_amplitudes / secs,
         "unit": "amplitudes/s",
         "complex_tflops": tflops,
@@ -746,7 +750,8 @@ def main():
         "dtype": head["dtype"],
         "data": "synthetic",
     }
-    out |= {k: head[k] for k in ("ms_per_step_graph", "complex_tflops", "mfma_peak_frac", "step_roofline_ms",
+    out |= {k: head[k] for k in ("ms_per_step_graph", "ms_per_pass", "ms_per_pass_median", "complex_tflops",
+                                 "mfma_peak_frac", "step_roofline_ms",
                                  "step_roofline_frac",
                                  "xeb", "error_vs_fp64", "bind_s", "autotune_s")}
     out["plan_s"] = t_plan
