@@ -37,16 +37,19 @@ for node v, and counts in the overflow the same way.
 Objective.  ``objective="flops"`` scores plans by the paper's loss: the
 complex MACs over all slices.  ``objective="time"`` (the default) scores
 them by a roofline estimate of the step times on one MI355X: a step moves
-8 * (w(v) 2^|v| + w(a) 2^|a| + w(b) 2^|b|) bytes and does 8 w(v) CMAC(v)
+eb * (w(v) 2^|v| + w(a) 2^|a| + w(b) 2^|b|) bytes and does 8 w(v) CMAC(v)
 flops, and takes the longer of bytes / HBM rate and flops / arithmetic rate
 (MFMA for GEMM-shaped steps, vector ALU otherwise), times 2^|S| when it is
-slice-dependent.  Both count the same arithmetic; the time objective also
+slice-dependent.  The rates and the element size eb are those of the
+precision the plan is for (``time_model``: complex64 by default, or
+complex-half, whose costly steps run on FP16 MFMA with 4-byte elements).  Both count the same arithmetic; the time objective also
 sees that wide steps over large tensors are bound by memory traffic, which
 the flop count does not.
 """
 
 from __future__ import annotations
 
+import contextlib
 import heapq
 import math
 from dataclasses import dataclass, field
@@ -136,22 +139,50 @@ def widths(tree: Tree, words: np.ndarray) -> List[int]:
     return out
 
 
-# sustained rates of the contraction kernels on one MI355X (complex64)
-RATE_MFMA = 100e12      # flop/s, FP32 MFMA GEMM steps
-RATE_VALU = 40e12       # flop/s, streaming steps
-RATE_HBM = 3.0e12       # byte/s, streaming steps
-LAUNCH_S = 3e-6         # per launch
+@dataclass(frozen=True)
+class TimeModel:
+    """Sustained rates of the contraction kernels on one MI355X."""
+    mfma: float           # flop/s of GEMM-shaped steps
+    valu: float           # flop/s of streaming steps
+    hbm: float            # byte/s
+    elem_bytes: float     # bytes per stored complex element
+    launch_s: float = 3e-6
+
+
+# complex64: FP32 MFMA on the GEMM steps; complex-half: FP16 MFMA (measured
+# 750 TFLOP/s on the 6x6 stem steps) and half the bytes (the costliest
+# steps are the ones a complex-half plan stores in FP16)
+TIME_MODELS = {
+    "c64": TimeModel(mfma=100e12, valu=40e12, hbm=3.0e12, elem_bytes=8.0),
+    "chalf": TimeModel(mfma=750e12, valu=40e12, hbm=3.3e12, elem_bytes=4.0),
+}
+_model = TIME_MODELS["c64"]
+
+
+@contextlib.contextmanager
+def time_model(precision: str):
+    """Score plans with the rates of `precision` ("c64" or "chalf") inside
+    the block (the default is complex64)."""
+    global _model
+    prev = _model
+    _model = TIME_MODELS[precision]
+    try:
+        yield _model
+    finally:
+        _model = prev
 
 
 def step_time(w: float, wa: float, wb: float, ra: int, rb: int, rc: int, k: int) -> float:
     """Estimated seconds of one slice of a pairwise step (see the module
-    docstring); ra >= rb are the operand ranks, k the contracted bits."""
+    docstring) under the current time model; ra >= rb are the operand ranks,
+    k the contracted bits."""
+    md = _model
     m, n = ra - k, rb - k
     flops = 8.0 * w * 2.0 ** (m + n + k)
-    by = 8.0 * (w * 2.0 ** rc + wa * 2.0 ** ra + wb * 2.0 ** rb)
-    rate = RATE_VALU
+    by = md.elem_bytes * (w * 2.0 ** rc + wa * 2.0 ** ra + wb * 2.0 ** rb)
+    rate = md.valu
     if n + k >= 8 and m >= 6 and n >= 5 and k >= 3:
-        rate = RATE_MFMA
+        rate = md.mfma
     elif m >= 6 and k >= 3 and n < 5:
         # fan-out tiles: output instances sharing an A instance fill the
         # 32 columns of one MFMA tile; the rate scales with the fill
@@ -159,8 +190,8 @@ def step_time(w: float, wa: float, wb: float, ra: int, rb: int, rc: int, k: int)
         group = w / max(wa, 1.0)
         if group >= 2.0 or (n == 4 and k >= 6):
             rows = math.ceil(group / slots)
-            rate = max(RATE_VALU, RATE_MFMA * group / (rows * slots))
-    return max(flops / rate, by / RATE_HBM) + LAUNCH_S
+            rate = max(md.valu, md.mfma * group / (rows * slots))
+    return max(flops / rate, by / md.hbm) + md.launch_s
 
 
 @dataclass

@@ -1,8 +1,12 @@
 """Writes c3_cap30.json: the contraction tree and sliced set of the 6x6
 depth-14 workload (2^14 amplitudes as 8 open legs x 64 bitstring groups,
 rank cap 30, at least 2^8 slices), found by the planner with the time
-objective from 32 greedy-family and 16 bisection candidates (seed 0).  The
-search takes a few minutes of host time, so the bench loads the stored
+objective under the complex-half time model (the workload's headline
+precision) from 32 greedy-family and 32 bisection candidates (seed 12).  The
+result depends strongly on the seed: seeds 0-17 gave estimates from 2.2 s
+to several minutes per pass; the three best were timed on the GPU and seed
+12's plan was the fastest (2.67 s against 2.79 and 2.97 s, complex-half).
+The search takes a few minutes of host time, so the bench loads the stored
 plan; any tree is valid input to the library.
 
     python -m paper_2212_04749_amd.plans.make_c3
@@ -26,12 +30,13 @@ def main() -> None:
     from workload import CONFIGS
     w = CONFIGS["C3"]
     net = build_network(w.circuit())
-    pl = planner.find_plan(net, w.bitstrings(), w.open_qubits, w.cap, seed=0, trials=32, partition_trials=16,
-                           min_slices=w.n_slices_target.bit_length() - 1, objective="time",
-                           progress=lambda m: print(m, flush=True))
+    with planner.time_model("chalf"):
+        pl = planner.find_plan(net, w.bitstrings(), w.open_qubits, w.cap, seed=12, trials=32, partition_trials=32,
+                               min_slices=w.n_slices_target.bit_length() - 1, objective="time",
+                               progress=lambda m: print(m, flush=True))
     out = {"pairs": [list(p) for p in pl.pairs], "sliced": list(pl.sliced), "cap": w.cap,
            "open_qubits": list(w.open_qubits), "est_seconds": pl.costs.time, "cmac_total": pl.costs.total,
-           "method": pl.method}
+           "method": pl.method, "time_model": "chalf"}
     with open(PATH, "w") as f:
         json.dump(out, f, separators=(",", ":"))
     print(len(pl.sliced), f"{pl.costs.total:.3e} CMAC", f"{pl.costs.time:.1f} s", pl.method)

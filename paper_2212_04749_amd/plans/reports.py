@@ -21,14 +21,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def _annotate(e: dict, net, words, open_qubits=(), min_slices: int = 0) -> dict:
-    stored = planner.plan_from(net, words, open_qubits, e["pairs"], e["sliced"], e.get("method", "stored"))
-    e["report"] = planner.report(stored, words)
-    try:
-        g = planner.greedy_plan(net, words, open_qubits, e["cap"], min_slices=min_slices,
-                                mem_cap=e.get("mem_cap"))
-        e["greedy_report"] = planner.report(g, words)
-    except ValueError as err:  # the greedy order cannot meet the caps
-        e["greedy_report"] = {"method": "greedy", "error": str(err)}
+    # time estimates under the model the plan was searched with
+    with planner.time_model(e.get("time_model", "c64")):
+        stored = planner.plan_from(net, words, open_qubits, e["pairs"], e["sliced"], e.get("method", "stored"))
+        e["report"] = planner.report(stored, words)
+        try:
+            g = planner.greedy_plan(net, words, open_qubits, e["cap"], min_slices=min_slices,
+                                    mem_cap=e.get("mem_cap"))
+            e["greedy_report"] = planner.report(g, words)
+        except ValueError as err:  # the greedy order cannot meet the caps
+            e["greedy_report"] = {"method": "greedy", "error": str(err)}
     return e
 
 
