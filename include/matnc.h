@@ -142,10 +142,12 @@ int matnc_plan_create(matnc_network net, const int *pairs, int n_sliced,
  *                                2^-11/sqrt(3)) to the amplitudes, so this is
  *                                the plan's precision budget; 0 keeps every
  *                                tensor in FP32; -1 = library default,
- *                                min(28, K / 282) for K = k * 2^n_open
+ *                                min(16, K / 282) for K = k * 2^n_open
  *                                amplitudes (the linear XEB of K amplitudes
- *                                moves by about 2 e / sqrt(K) for relative
- *                                errors of rms e).  Ignored for MATNC_C64.
+ *                                moves by about 2 e / sqrt(K) for independent
+ *                                relative errors of rms e; the cap of 16
+ *                                keeps a margin for correlated ones).
+ *                                Ignored for MATNC_C64.
  * Errors: as matnc_plan_create; MATNC_E_INVALID for a null opts or
  * half_nodes < -1.
  */

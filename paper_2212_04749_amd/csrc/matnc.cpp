@@ -95,10 +95,13 @@ constexpr uint64_t kAlign = 256;
 // amplitudes carry relative errors of rms e ~ 2.8e-4 sqrt(N); the linear XEB
 // of K amplitudes then moves by about 2 e / sqrt(K) (independent errors,
 // Porter-Thomas amplitudes).  Keeping three times that within the 1e-4 XEB
-// bar gives N <= K / kAmpsPerHalfNode; kMaxHalfNodes keeps e below half of
-// the 3e-3 amplitude bar.
+// bar gives N <= K / kAmpsPerHalfNode.  The errors are not independent in
+// general (which tensors are rounded matters): on the 6x6 depth-14 workload
+// the XEB of 16 384 amplitudes stays within 4.5e-5 of complex64's up to 24
+// FP16 tensors and jumps to 1.5e-4 at 28, while the pass gets only 2%
+// faster above 12; kMaxHalfNodes = 16 keeps that margin and e near 1e-3.
 constexpr int64_t kAmpsPerHalfNode = 282;
-constexpr int kMaxHalfNodes = 28;
+constexpr int kMaxHalfNodes = 16;
 
 // bytes per stored element of node v: complex64 (8) unless the plan is
 // complex-half and v is an FP16-stored branch tensor (4)

@@ -4,7 +4,7 @@ accumulation, FP64 slice-sum) against the FP64 oracle.
 Bar: ||a - a_ref|| / ||a_ref|| <= 3e-3 over the batch and |XEB - XEB_ref|
 <= 1e-4.  The intermediates whose steps carry the most estimated time are
 stored in FP16, as many as the batch size allows (the plan's precision
-budget, min(28, K / 282) tensors for K amplitudes); leaves and the rest stay
+budget, min(16, K / 282) tensors for K amplitudes); leaves and the rest stay
 FP32.
 """
 
