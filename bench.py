@@ -145,6 +145,8 @@ def workload_description(name, w, info, spec, e):
     shape = f"{g.rows}x{g.cols}" + (f" minus {len(g.removed)} site" if g.removed else "")
     greedy = (e or {}).get("greedy_report") or {}
     plan_txt = f"; plan: {spec.method}"
+    if (e or {}).get("time_model"):
+        plan_txt += f", searched under the {e['time_model']} time model"
     if greedy.get("cmac_total"):
         plan_txt += f" (the greedy order sliced to the same cap: {greedy['cmac_total']:.2e} CMAC)"
     return {
@@ -163,6 +165,7 @@ def workload_description(name, w, info, spec, e):
         "cmac_total": float(info.cmac_total),
         "kS_over_Sk": float(info.n_unique * info.cmac_single / info.cmac_multi),
         "plan": spec.method,
+        "plan_time_model": (e or {}).get("time_model", "c64") if e else None,
         "greedy_plan": greedy or None,
     }
 
