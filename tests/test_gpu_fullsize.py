@@ -144,7 +144,7 @@ def test_c3_size_permutation_every_fp16_configuration(tmp_path):
 
 @pytest.mark.parametrize("precision,tol", [("c64", 1e-5), ("chalf", 3e-3)])
 def test_c4_size_permutation_circuit(precision, tol):
-    # the 53-qubit workload's network structure and stored plan (8192
+    # the 53-qubit workload's network structure and stored plan (4096
     # slices), on a permutation circuit: the one contributing slice gives
     # the exact amplitudes (modulus 2^-26.5, which also exercises the
     # complex-half exponents) and a neighbouring slice gives zero
