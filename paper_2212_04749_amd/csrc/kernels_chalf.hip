@@ -37,6 +37,9 @@ __device__ __forceinline__ uint32_t h2bits(__half2 h) {
   return u;
 }
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// four output words at word offset i (a multiple of 4) as one 16-byte store
+__device__ __forceinline__ void stg_u32x4(uint64_t base, uint64_t i, u32x4 v) { gmem<u32x4>(base)[i >> 2] = v; }
 
 // an FP32 (re, im) pair as half2 bits, scaled by c and rounded to nearest
 __device__ __forceinline__ uint32_t f32pair_to_h2bits(u32x2 raw, float c) {
@@ -372,39 +375,75 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
     const float f = ldexpf(1.f, 15 - ex);
     const int e_out = ea + eb + ex - 15;
     float mx = 0.f;
+    // Lane l of half-wave h holds the column pairs 4c + 2h, 4c + 2h + 1 of
+    // its m.  In plain tiles whose n bits 0 and 1 are the output's two lowest
+    // storage positions, the half-waves swap pairs (v_permlane32_swap) so
+    // that each lane holds four consecutive columns and writes them as one
+    // 16-byte store; a wave then writes 32 runs of 32 bytes instead of 64
+    // scattered words.  The test is uniform over the workgroup.
+    if (!FAN && s_cn[1] - s_cn[0] == 1u && s_cn[2] - s_cn[0] == 2u) {
 #pragma unroll
-    for (int q = 0; q < RN; ++q) {
+      for (int q = 0; q < RN; ++q) {
 #pragma unroll
-      for (int rr = 0; rr < 8; ++rr) {
-        const int r = 2 * rr;
-        const int row = 8 * (rr >> 1) + 4 * half + 2 * (rr & 1);
-        const int nl = (wn * RN + q) * 16 + (row >> 1);  // column within the tile
-        const uint32_t ocn = s_cn[nl];
-        uint64_t dst = pc;
-        bool live = true;
-        float fo = f;
-        int g = 0;
-        if (FAN) {
-          g = nl >> d.nbits;
-          const uint64_t cbs = s_cbase[g];  // uniform over the 32 lanes of a half-wave (one n)
-          live = cbs != 0;
-          dst = ws + cbs;
-          fo = s_f[g];
+        for (int c = 0; c < 2; ++c) {
+          // hv: columns 8c + 2h + {0, 1, 4, 5} of this lane's m
+          uint32_t hv[RM][4];
+#pragma unroll
+          for (int r4 = 0; r4 < 4; ++r4) {
+            const int r = 2 * (4 * c + r4);
+#pragma unroll
+            for (int i = 0; i < RM; ++i) {
+              const __half2 h = __float22half2_rn(make_float2(acc[i][q][r] * f, acc[i][q][r + 1] * f));
+              hv[i][r4] = h2bits(h);
+              const float2 back = __half22float2(h);
+              mx = fmaxf(mx, fmaxf(fabsf(back.x), fabsf(back.y)));
+            }
+          }
+          // after the swaps half-wave h holds columns 8c + 4h + {0, 1, 2, 3}
+          const uint32_t ocn = s_cn[(wn * RN + q) * 16 + 8 * c + 4 * half];
+#pragma unroll
+          for (int i = 0; i < RM; ++i) {
+            const auto x0 = __builtin_amdgcn_permlane32_swap(hv[i][0], hv[i][2], false, false);
+            const auto x1 = __builtin_amdgcn_permlane32_swap(hv[i][1], hv[i][3], false, false);
+            stg_u32x4(pc, om[i] + ocn, u32x4{x0[0], x1[0], x0[1], x1[1]});
+          }
         }
-        float v = 0.f;
+      }
+    } else {
 #pragma unroll
-        for (int i = 0; i < RM; ++i) {
-          const __half2 h = __float22half2_rn(make_float2(acc[i][q][r] * fo, acc[i][q][r + 1] * fo));
-          if (live) stg_u32(dst, om[i] + ocn, h2bits(h));
-          const float2 back = __half22float2(h);
-          v = fmaxf(v, fmaxf(fabsf(back.x), fabsf(back.y)));
-        }
-        if (FAN) {
+      for (int q = 0; q < RN; ++q) {
 #pragma unroll
-          for (int o2 = 16; o2 > 0; o2 >>= 1) v = fmaxf(v, __shfl_xor(v, o2));
-          if (l32 == 0 && live) atomicMax(&s_mx[g], __float_as_uint(v));
-        } else {
-          mx = fmaxf(mx, v);
+        for (int rr = 0; rr < 8; ++rr) {
+          const int r = 2 * rr;
+          const int row = 8 * (rr >> 1) + 4 * half + 2 * (rr & 1);
+          const int nl = (wn * RN + q) * 16 + (row >> 1);  // column within the tile
+          const uint32_t ocn = s_cn[nl];
+          uint64_t dst = pc;
+          bool live = true;
+          float fo = f;
+          int g = 0;
+          if (FAN) {
+            g = nl >> d.nbits;
+            const uint64_t cbs = s_cbase[g];  // uniform over the 32 lanes of a half-wave (one n)
+            live = cbs != 0;
+            dst = ws + cbs;
+            fo = s_f[g];
+          }
+          float v = 0.f;
+#pragma unroll
+          for (int i = 0; i < RM; ++i) {
+            const __half2 h = __float22half2_rn(make_float2(acc[i][q][r] * fo, acc[i][q][r + 1] * fo));
+            if (live) stg_u32(dst, om[i] + ocn, h2bits(h));
+            const float2 back = __half22float2(h);
+            v = fmaxf(v, fmaxf(fabsf(back.x), fabsf(back.y)));
+          }
+          if (FAN) {
+#pragma unroll
+            for (int o2 = 16; o2 > 0; o2 >>= 1) v = fmaxf(v, __shfl_xor(v, o2));
+            if (l32 == 0 && live) atomicMax(&s_mx[g], __float_as_uint(v));
+          } else {
+            mx = fmaxf(mx, v);
+          }
         }
       }
     }
