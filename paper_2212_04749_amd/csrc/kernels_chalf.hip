@@ -40,6 +40,8 @@ __device__ __forceinline__ uint32_t h2bits(__half2 h) {
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // four output words at word offset i (a multiple of 4) as one 16-byte store
 __device__ __forceinline__ void stg_u32x4(uint64_t base, uint64_t i, u32x4 v) { gmem<u32x4>(base)[i >> 2] = v; }
+// two output words at word offset i (even) as one 8-byte store
+__device__ __forceinline__ void stg_u32x2(uint64_t base, uint64_t i, u32x2 v) { gmem<u32x2>(base)[i >> 1] = v; }
 
 // an FP32 (re, im) pair as half2 bits, scaled by c and rounded to nearest
 __device__ __forceinline__ uint32_t f32pair_to_h2bits(u32x2 raw, float c) {
@@ -406,6 +408,23 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
             const auto x0 = __builtin_amdgcn_permlane32_swap(hv[i][0], hv[i][2], false, false);
             const auto x1 = __builtin_amdgcn_permlane32_swap(hv[i][1], hv[i][3], false, false);
             stg_u32x4(pc, om[i] + ocn, u32x4{x0[0], x1[0], x0[1], x1[1]});
+          }
+        }
+      }
+    } else if (!FAN && s_cn[1] - s_cn[0] == 1u) {
+      // n bit 0 alone lowest: each lane's column pair is one 8-byte store
+#pragma unroll
+      for (int q = 0; q < RN; ++q) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const uint32_t ocn = s_cn[(wn * RN + q) * 16 + 4 * c + 2 * half];
+#pragma unroll
+          for (int i = 0; i < RM; ++i) {
+            const __half2 h0 = __float22half2_rn(make_float2(acc[i][q][4 * c] * f, acc[i][q][4 * c + 1] * f));
+            const __half2 h1 = __float22half2_rn(make_float2(acc[i][q][4 * c + 2] * f, acc[i][q][4 * c + 3] * f));
+            stg_u32x2(pc, om[i] + ocn, u32x2{h2bits(h0), h2bits(h1)});
+            const float2 b0 = __half22float2(h0), b1 = __half22float2(h1);
+            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(b0.x), fabsf(b0.y)), fmaxf(fabsf(b1.x), fabsf(b1.y))));
           }
         }
       }
