@@ -428,6 +428,41 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
           }
         }
       }
+    } else if (!FAN && s_cn[1] - s_cn[0] == 2u && tlook(tab + TAB_CM * kTabSize, 1u) == 1u) {
+      // m bit 0 lowest, n bit 0 next: lanes 2j and 2j + 1 (m bit 0 = 0, 1)
+      // exchange column pairs (DPP) so that each holds the 2 x 2 block of one
+      // pair -- four consecutive words, one 16-byte store -- the even lane
+      // for column pair 4c + 2h (c even), the odd lane for 4(c + 1) + 2h
+      const bool odd = (l32 & 1) != 0;
+#pragma unroll
+      for (int q = 0; q < RN; ++q) {
+#pragma unroll
+        for (int p2 = 0; p2 < 2; ++p2) {
+          const int cs = 2 * p2 + (odd ? 1 : 0);  // the column group this lane stores
+          const uint32_t ocn = s_cn[(wn * RN + q) * 16 + 4 * cs + 2 * half];
+#pragma unroll
+          for (int i = 0; i < RM; ++i) {
+            uint32_t w[2][2];  // [group 2 p2 + e][n bit 0]
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+              const int r = 4 * (2 * p2 + e);
+              const __half2 h0 = __float22half2_rn(make_float2(acc[i][q][r] * f, acc[i][q][r + 1] * f));
+              const __half2 h1 = __float22half2_rn(make_float2(acc[i][q][r + 2] * f, acc[i][q][r + 3] * f));
+              w[e][0] = h2bits(h0);
+              w[e][1] = h2bits(h1);
+              const float2 b0 = __half22float2(h0), b1 = __half22float2(h1);
+              mx = fmaxf(mx, fmaxf(fmaxf(fabsf(b0.x), fabsf(b0.y)), fmaxf(fabsf(b1.x), fabsf(b1.y))));
+            }
+            // send the group the partner stores, keep the own one
+            const uint32_t s0 = odd ? w[0][0] : w[1][0];
+            const uint32_t s1 = odd ? w[0][1] : w[1][1];
+            const uint32_t r0 = (uint32_t)__builtin_amdgcn_mov_dpp((int)s0, 0xB1, 0xF, 0xF, false);  // lane ^ 1
+            const uint32_t r1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)s1, 0xB1, 0xF, 0xF, false);
+            const u32x4 v = odd ? u32x4{r0, w[1][0], r1, w[1][1]} : u32x4{w[0][0], r0, w[0][1], r1};
+            stg_u32x4(pc, om[i] - (odd ? 1u : 0u) + ocn, v);
+          }
+        }
+      }
     } else {
 #pragma unroll
       for (int q = 0; q < RN; ++q) {
