@@ -30,7 +30,7 @@ MEM_CAP = 33
 HERE = os.path.dirname(os.path.abspath(__file__))
 PATH = os.path.join(HERE, f"c5_cap{CAP}.json")
 # circuit -> seed of its search under the complex-half time model
-CHALF_SEEDS = {"C5.18": 4, "C5.9": 4, "C5.31": 2, "C5.20": 4, "C5.10": 2}
+CHALF_SEEDS = {"C5.18": 13, "C5.9": 4, "C5.31": 2, "C5.20": 4, "C5.10": 2, "C5.1": 4, "C5.19": 4, "C5.17": 3}
 
 
 def _plan_one(name: str):
