@@ -614,8 +614,9 @@ def run_uneven(args) -> None:
         "dtype": PRECISION_NAME[prec], "data": "synthetic",
         "complex_tflops": 8 * cmac / secs / 1e12,
         "config": {"workload": f"C5: uneven batch of {len(sel)} seeded grid RQCs (20-36 qubits, depth 10-16, "
-                               f"256-4096 bitstrings), stored plans at rank cap 30, one queue, one workspace, "
-                               f"one graph",
+                               f"256-4096 bitstrings), stored plans at rank cap 30 ("
+                               f"{sum(e.get('time_model') == 'chalf' for e in plans.values())} searched under the "
+                               f"chalf time model, the others under c64), one queue, one workspace, one graph",
                    "circuits": len(sel), "left_out": [w.name for w, _ in skipped],
                    "shared_workspace_bytes": int(q.workspace.numel()),
                    "amplitudes": n_amps, "precision": prec},
