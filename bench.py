@@ -372,6 +372,8 @@ def run_leg(api, torch, name, w, net, spec, precision, batch, steps, warmup, arg
                             "projected_job_s": secs, "per_slice_ms": ms_slices / n_timed,
                             "prologue_ms": max(0.0, ms_step - ms_slices)}),
         "roofline": roof,
+        # the random circuit's amplitudes of a full pass (removed before output)
+        "_amps": amps_c if full else None,
     }
     run.close()
     del amps
@@ -771,6 +773,17 @@ def main():
             # the random circuit's linear XEB over the whole batch, the two
             # precisions on the same plan and bitstrings
             out["xeb_vs_" + PRECISION_NAME[other].replace("-", "_")] = abs(head["xeb"] - leg["xeb"])
+        if head["_amps"] is not None and leg["_amps"] is not None:
+            # complex-half against complex64 on the random circuit itself (its
+            # complex64 error is ~1e-6 on the workloads the oracle reaches)
+            h, c = (head["_amps"], leg["_amps"]) if args.precision == "chalf" else (leg["_amps"], head["_amps"])
+            d = h - c
+            rms = float(np.sqrt(np.mean(np.abs(c) ** 2)))
+            out["complex_half_vs_complex64"] = {
+                "rel_diff": float(np.linalg.norm(d) / np.linalg.norm(c)),
+                "max_abs_diff_over_rms": float(np.max(np.abs(d)) / rms), "amplitudes": int(c.size)}
+        leg.pop("_amps")
+    head.pop("_amps")
     if name == "C3" and not args.no_secondary:
         # the 5x6 workload (4096 bitstrings, stored plan) in both precisions
         w2 = CONFIGS["C2"]
@@ -780,6 +793,7 @@ def main():
         sec = {}
         for prec in ("c64", "chalf"):
             sec[PRECISION_NAME[prec]] = run_leg(api, torch, "C2", w2, net2, spec2, prec, 4, 3, 1, args, e2)
+            sec[PRECISION_NAME[prec]].pop("_amps")
         out["secondary"] = {"C2": sec}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

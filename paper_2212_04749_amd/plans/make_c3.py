@@ -2,12 +2,14 @@
 depth-14 workload (2^14 amplitudes as 8 open legs x 64 bitstring groups,
 rank cap 30, at least 2^8 slices), found by the planner with the time
 objective under the complex-half time model (the workload's headline
-precision) from 32 greedy-family and 32 bisection candidates (seed 12).  The
-result depends strongly on the seed: seeds 0-17 gave estimates from 2.2 s
-to several minutes per pass; the three best were timed on the GPU and seed
-12's plan was the fastest (2.67 s against 2.79 and 2.97 s, complex-half).
-The search takes a few minutes of host time, so the bench loads the stored
-plan; any tree is valid input to the library.
+precision) from 32 greedy-family and 32 bisection candidates (seed 19).  The
+result depends strongly on the seed: seeds 0-29 gave estimates from 1.6 s
+to minutes per pass; the best were timed on the GPU.  Seed 19's plan
+(9.6e13 CMAC) runs 1.71 s per pass against 2.44 s for seed 12's (1.5e14
+CMAC) and 2.40 s for seed 22's, in complex-half, and its complex-half
+amplitudes of the random circuit stay within 1.2e-3 of complex64's (XEB
+within 7e-6).  The search takes a few minutes of host time, so the bench
+loads the stored plan; any tree is valid input to the library.
 
     python -m paper_2212_04749_amd.plans.make_c3
 """
@@ -31,7 +33,7 @@ def main() -> None:
     w = CONFIGS["C3"]
     net = build_network(w.circuit())
     with planner.time_model("chalf"):
-        pl = planner.find_plan(net, w.bitstrings(), w.open_qubits, w.cap, seed=12, trials=32, partition_trials=32,
+        pl = planner.find_plan(net, w.bitstrings(), w.open_qubits, w.cap, seed=19, trials=32, partition_trials=32,
                                min_slices=w.n_slices_target.bit_length() - 1, objective="time",
                                progress=lambda m: print(m, flush=True))
     out = {"pairs": [list(p) for p in pl.pairs], "sliced": list(pl.sliced), "cap": w.cap,
