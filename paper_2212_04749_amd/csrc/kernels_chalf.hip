@@ -378,11 +378,13 @@ __global__ __launch_bounds__(64 * WM * WN) void k_mfma_h(NodeDesc d, uint64_t ws
     const int e_out = ea + eb + ex - 15;
     float mx = 0.f;
     // Lane l of half-wave h holds the column pairs 4c + 2h, 4c + 2h + 1 of
-    // its m.  In plain tiles whose n bits 0 and 1 are the output's two lowest
-    // storage positions, the half-waves swap pairs (v_permlane32_swap) so
-    // that each lane holds four consecutive columns and writes them as one
-    // 16-byte store; a wave then writes 32 runs of 32 bytes instead of 64
-    // scattered words.  The test is uniform over the workgroup.
+    // its m.  Plain tiles pick their stores from the output's lowest storage
+    // positions (a test uniform over the workgroup): where columns, or a
+    // column and m bit 0, are adjacent in memory, lanes combine values into
+    // 8- or 16-byte stores; otherwise (m bits lowest, so that neighbouring
+    // lanes already write consecutive words) each value is one 4-byte store.
+    // n bits 0 and 1 lowest: the half-waves swap pairs (v_permlane32_swap) so
+    // that each lane holds four consecutive columns, one 16-byte store.
     if (!FAN && s_cn[1] - s_cn[0] == 1u && s_cn[2] - s_cn[0] == 2u) {
 #pragma unroll
       for (int q = 0; q < RN; ++q) {
