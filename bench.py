@@ -140,7 +140,7 @@ def stored_plan(name, net, words, open_qubits):
     return plan, e
 
 
-def workload_description(name, w, info, spec, e):
+def workload_description(name, w, info, spec, e, net=None):
     g = w.grid
     shape = f"{g.rows}x{g.cols}" + (f" minus {len(g.removed)} site" if g.removed else "")
     greedy = (e or {}).get("greedy_report") or {}
@@ -167,7 +167,19 @@ def workload_description(name, w, info, spec, e):
         "plan": spec.method,
         "plan_time_model": (e or {}).get("time_model", "c64") if e else None,
         "greedy_plan": greedy or None,
-    }
+        "workspace_bytes": int(info.workspace_bytes),
+    } | ({} if net is None else {"reuse_tree_memory": reuse_tree_memory(net, w, spec)})
+
+
+def reuse_tree_memory(net, w, spec):
+    """The paper's breadth- and depth-first memory figures of the plan's reuse
+    tree (planner.memory_figures, per slice, in tensor elements) beside the
+    library's workspace, which holds every node's instances of a slice batch."""
+    from paper_2212_04749_amd import planner
+    st = planner.Structure.from_network(net, w.open_qubits)
+    tree = planner.build_tree(st, list(spec.pairs), sum(1 << i for i in spec.sliced))
+    m = planner.memory_figures(tree, w.bitstrings())
+    return {"M_BFT_elements": m["M_BFT"], "M_DFT_elements": m["M_DFT"], "layers": len(m["layers"])}
 
 
 def _golden_amps(g):
@@ -366,7 +378,7 @@ def run_leg(api, torch, name, w, net, spec, precision, batch, steps, warmup, arg
         "error_vs_fp64": err,
         "bind_s": t_bind,
         "autotune_s": t_tune,
-        "config": workload_description(name, w, info, spec, e) | {"slice_batch": batch, "precision": precision,
+        "config": workload_description(name, w, info, spec, e, net) | {"slice_batch": batch, "precision": precision,
                                                                      "key_chunks": int(info.n_chunks)}
         | ({} if full else {"slices_timed": [s_begin, s_end], "value_is_projected": True,
                             "projected_job_s": secs, "per_slice_ms": ms_slices / n_timed,

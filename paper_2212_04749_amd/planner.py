@@ -708,6 +708,43 @@ def report(plan: Plan, words: np.ndarray) -> dict:
             "n_slices": 2 ** c.n_sliced, "max_rank": c.max_rank, "est_seconds": c.time, "method": plan.method}
 
 
+def stem_path(tree: Tree) -> List[int]:
+    """The stem of a contraction tree, bottom-up: from the root down to a leaf
+    through the child with more leaves below it (ties: the first of the pair).  On a
+    path-shaped order (each step absorbs one leaf) this is the order itself."""
+    n = tree.n_tensors
+    path = []
+    v = tree.root
+    while v >= n:
+        path.append(v)
+        a, b = tree.pairs[v - n]
+        ca, cb = bin(tree.leafsets[a]).count("1"), bin(tree.leafsets[b]).count("1")
+        v = a if ca >= cb else b
+    path.append(v)
+    return path[::-1]
+
+
+def memory_figures(tree: Tree, words: np.ndarray) -> dict:
+    """Memory of the two traversals of the reuse tree (Supplementary
+    Sec. III.C), in tensor elements, along the stem s_0 (a leaf), s_1, ...
+    of the tree.  The reuse tree branches at each stem step j whose width
+    grows, w(s_j) > w(s_{j-1}): what s_j absorbs carries closed outputs not
+    seen before.  Its layer l holds the nodes at that point, one per
+    distinct prefix, w_l = w(s_{j-1}) of them (w_1 = 1 at the end of the
+    trunk), and each stores the tensor immediately before it, s_{j-1}, of
+    rank d_l = |idx(s_{j-1})|, for its children to reuse.  Breadth first,
+    all of one layer's tensors are held at once: M^BFT = max_l w_l 2^{d_l}.
+    Depth first, one per layer on the current root-to-leaf path:
+    M^DFT = sum_l 2^{d_l}; the twig after the last branching stores nothing.
+    A sliced index is fixed in every slice, so a tree built with a sliced
+    set gives the figures of one slice."""
+    w = widths(tree, words)
+    s = stem_path(tree)
+    layers = [(w[s[j - 1]], bin(tree.masks[s[j - 1]]).count("1")) for j in range(1, len(s)) if w[s[j]] > w[s[j - 1]]]
+    return {"layers": layers, "M_BFT": max((wl << d for wl, d in layers), default=0),
+            "M_DFT": sum(1 << d for _, d in layers)}
+
+
 # --------------------------------------------------------------------------
 # local refinement: subtree reconfiguration
 #
