@@ -14,7 +14,10 @@ multi-amplitude method:
 * S = sum_v CMAC(v) (single-amplitude cost) and S_k = sum_v w(v) CMAC(v)
   (multi-amplitude cost with optimal reuse, Eq. (1));
 * with a sliced set, nodes that see no sliced index run once, the others once
-  per slice.
+  per slice;
+* M^BFT and M^DFT (Supplementary Sec. III.C), the memory of the breadth- and
+  depth-first traversals of the reuse tree along the tree's stem
+  (``memory_figures``).
 
 Order search.  The paper searches orders with the multi-amplitude cost S_k
 as the loss (Supplementary Sec. IV.A).  Here a seeded randomised search
