@@ -160,19 +160,28 @@ TIME_MODELS = {
     "chalf": TimeModel(mfma=750e12, valu=40e12, hbm=3.3e12, elem_bytes=4.0),
 }
 _model = TIME_MODELS["c64"]
+# complex-half precision budget of the plan being scored: None prices every
+# step at complex-half rates; N prices only the N steps with the most
+# estimated complex64 time so (the library's choice of FP16 tensors), the
+# others at complex64 rates
+_half_budget: Optional[int] = None
 
 
 @contextlib.contextmanager
-def time_model(precision: str):
+def time_model(precision: str, half_budget: Optional[int] = None):
     """Score plans with the rates of `precision` ("c64" or "chalf") inside
-    the block (the default is complex64)."""
-    global _model
-    prev = _model
+    the block (the default is complex64).  For "chalf", `half_budget` is the
+    number of intermediates the plan will store in FP16 (the library's
+    default is min(16, k / 282) for k amplitudes); None assumes every step
+    runs at complex-half rates."""
+    global _model, _half_budget
+    prev = (_model, _half_budget)
     _model = TIME_MODELS[precision]
+    _half_budget = half_budget if precision == "chalf" else None
     try:
         yield _model
     finally:
-        _model = prev
+        _model, _half_budget = prev
 
 
 def step_time(w: float, wa: float, wb: float, ra: int, rb: int, rc: int, k: int) -> float:
@@ -211,10 +220,14 @@ class Costs:
 
 
 def costs(st: Structure, tree: Tree, w: Sequence[int], sliced_mask: int = 0) -> Costs:
+    global _model
     n = st.n_tensors
     dep = [bool(st.leaf_masks[t] & sliced_mask) for t in range(n)]
     S = Sk = total = tm = 0.0
     nsl = bin(sliced_mask).count("1")
+    budget = _half_budget
+    t32: List[float] = []
+    t16: List[float] = []
     for j, (a, b) in enumerate(tree.pairs):
         v = n + j
         dep.append(dep[a] or dep[b])
@@ -227,8 +240,17 @@ def costs(st: Structure, tree: Tree, w: Sequence[int], sliced_mask: int = 0) -> 
         wa, wb = w[a], w[b]
         if rb > ra:
             ra, rb, wa, wb = rb, ra, wb, wa
-        tm += mult * step_time(w[v], wa, wb, ra, rb, tree.masks[v].bit_count(),
-                               (tree.masks[a] & tree.masks[b]).bit_count())
+        args = (w[v], wa, wb, ra, rb, tree.masks[v].bit_count(), (tree.masks[a] & tree.masks[b]).bit_count())
+        if budget is None:
+            tm += mult * step_time(*args)
+        else:
+            t16.append(mult * step_time(*args))
+            model, _model = _model, TIME_MODELS["c64"]
+            t32.append(mult * step_time(*args))
+            _model = model
+    if budget is not None:
+        top = sorted(range(len(t32)), key=lambda i: -t32[i])[:budget]
+        tm = sum(t32) + sum(t16[i] - t32[i] for i in top)
     mr = max(m.bit_count() for m in tree.masks)
     return Costs(S, Sk, total, mr, nsl, tm)
 

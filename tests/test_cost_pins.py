@@ -114,3 +114,49 @@ def test_slice_refiner_reaches_a_local_optimum_of_the_multi_amplitude_loss():
             trial[pos] = j
             v = loss(trial)
             assert v is None or v >= c2.total * (1 - 1e-9)
+
+
+def test_complex_half_budget_time_estimate():
+    # the complex-half time estimate under a precision budget N prices the N
+    # steps with the most estimated complex64 time at complex-half rates and
+    # the rest at complex64 rates: N = 0 is the complex64 estimate, N at or
+    # above the step count the all-FP16 one, and each step moved between
+    # the two changes the total by its own difference
+    from paper_2212_04749_amd import planner as P
+    from paper_2212_04749_amd.circuit_tn import build_network
+    net = build_network(random_circuit(GridSpec(4, 4), 10, 3))
+    words = uniform_bitstrings(16, 300, 9)
+    pl = P.find_plan(net, words, (), 10, seed=0, trials=2)
+    st = P.Structure.from_network(net, ())
+    mask = sum(1 << i for i in pl.sliced)
+    tree = P.build_tree(st, pl.pairs, mask)
+    w = P.widths(P.build_tree(st, pl.pairs), words)
+
+    def est(*model):
+        with P.time_model(*model):
+            return P.costs(st, tree, w, mask).time
+
+    def per_step(model):
+        n, nsl, dep, out = st.n_tensors, bin(mask).count("1"), [bool(m & mask) for m in st.leaf_masks], []
+        for j, (a, b) in enumerate(tree.pairs):
+            dep.append(dep[a] or dep[b])
+            ra, rb, wa, wb = tree.masks[a].bit_count(), tree.masks[b].bit_count(), w[a], w[b]
+            if rb > ra:
+                ra, rb, wa, wb = rb, ra, wb, wa
+            with P.time_model(model):
+                t = P.step_time(w[n + j], wa, wb, ra, rb, tree.masks[n + j].bit_count(),
+                                (tree.masks[a] & tree.masks[b]).bit_count())
+            out.append(t * (2.0 ** nsl if dep[-1] else 1.0))
+        return out
+
+    t32, t16 = per_step("c64"), per_step("chalf")
+    assert np.isclose(est("c64"), sum(t32)) and np.isclose(est("chalf"), sum(t16))
+    assert np.isclose(est("chalf", 0), sum(t32)) and np.isclose(est("chalf", len(t32)), sum(t16))
+    order = sorted(range(len(t32)), key=lambda i: -t32[i])
+    for N in (1, 3, 5):
+        want = sum(t32) + sum(t16[i] - t32[i] for i in order[:N])
+        assert np.isclose(est("chalf", N), want)
+    # the budget never prices a step above its complex64 time here
+    assert est("chalf", 5) <= est("chalf", 0) + 1e-12
+    # the default model is restored after the block
+    assert np.isclose(est("c64"), P.costs(st, tree, w, mask).time)
