@@ -3,7 +3,7 @@ depth-14 workload (2^14 amplitudes as 8 open legs x 64 bitstring groups,
 rank cap 30, at least 2^8 slices), found by the planner with the time
 objective under the complex-half time model (the workload's headline
 precision) from 32 greedy-family and 32 bisection candidates (seed 19).  The
-result depends strongly on the seed: seeds 0-53 gave estimates from 1.6 s
+result depends strongly on the seed: seeds 0-77 gave estimates from 1.6 s
 to minutes per pass; the best were timed on the GPU.  Seed 19's plan
 (9.6e13 CMAC) runs 1.71 s per pass against 2.44 s for seed 12's (1.5e14
 CMAC) and 2.40 s for seed 22's, in complex-half, and its complex-half
